@@ -1,0 +1,226 @@
+"""ORACLE — test infrastructure, not product code.
+
+Python binding of the plain FP64 CPU implementation in ``mhd_oracle.cpp``
+(one step of the finite-volume ideal-MHD scheme: primitive recovery, PLM,
+HLL/HLLD, upwind constrained-transport EMF, SSP-RK2, CFL time step), plus the
+exact Euler Riemann solver used to pin it (``exact_euler``).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline
+leg may import this package. It shares no code with the GPU library.
+
+Arrays follow the state layout of the method: one float64 array of shape
+``(8, nz, ny, nx)`` holding (rho, m_x, m_y, m_z, E, b_x, b_y, b_z); b_d lives
+on the lower d-face of each cell; in 2D field 7 is the cell-centred B_z.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mhd_oracle.cpp")
+_SO = os.path.join(_HERE, "libmhd_oracle.so")
+
+LIMITERS = {"minmod": 0, "vanleer": 1}
+SOLVERS = {"hlld": 0, "hll": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
+class OCfg(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("xmin", ctypes.c_double), ("xmax", ctypes.c_double),
+        ("ymin", ctypes.c_double), ("ymax", ctypes.c_double),
+        ("zmin", ctypes.c_double), ("zmax", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("limiter", ctypes.c_int32), ("riemann", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("nthreads", ctypes.c_int32),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off",
+               "-Wall", "-Wextra", "-shared", "-fPIC", _SRC, "-o", tmp]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.POINTER
+        dp = P(ctypes.c_double)
+        cp = P(OCfg)
+        for name, args, res in [
+            ("oracle_rhs", [cp, dp, dp], ctypes.c_int),
+            ("oracle_step", [cp, dp, ctypes.c_double], ctypes.c_int),
+            ("oracle_dt", [cp, dp, dp], ctypes.c_int),
+            ("oracle_run", [cp, dp, ctypes.c_int, dp], ctypes.c_int),
+            ("oracle_run_dts", [cp, dp, ctypes.c_int, dp], ctypes.c_int),
+            ("oracle_step_jvp", [cp, dp, dp, ctypes.c_double, ctypes.c_double], ctypes.c_int),
+            ("oracle_divb", [cp, dp, dp], ctypes.c_int),
+            ("oracle_prim", [cp, dp, dp], ctypes.c_int),
+            ("oracle_riemann", [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
+                                ctypes.c_double, dp], ctypes.c_int),
+            ("oracle_flux", [ctypes.c_double, dp, ctypes.c_double, dp, dp], ctypes.c_int),
+            ("oracle_slope", [ctypes.c_int, ctypes.c_double, ctypes.c_double], ctypes.c_double),
+            ("oracle_fast_speed", [ctypes.c_double] * 6, ctypes.c_double),
+            ("oracle_uct", [dp], ctypes.c_double),
+        ]:
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Unphysical(OracleError):
+    pass
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc: int):
+    if rc == -1:
+        raise OracleError("oracle: invalid argument")
+    if rc == -4:
+        raise Unphysical("oracle: unphysical state (rho <= 0, p <= 0 or non-finite)")
+
+
+def cfg_from(setup: dict, nthreads: int = 0, **over) -> OCfg:
+    """Build the oracle configuration from a workload description dict."""
+    s = dict(setup)
+    s.update(over)
+    box = s["box"]
+    return OCfg(int(s["dim"]), int(s["nx"]), int(s["ny"]), int(s["nz"]),
+                box[0], box[1], box[2], box[3], box[4], box[5],
+                float(s["gamma"]), float(s["cfl"]),
+                LIMITERS[s["limiter"]], SOLVERS[s["riemann"]],
+                PRECISIONS[s.get("precision", "fp64")], int(nthreads))
+
+
+def _shape(c: OCfg):
+    return (8, c.nz, c.ny, c.nx)
+
+
+def _state(c: OCfg, U) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    if U.shape != _shape(c):
+        raise OracleError("state shape %s, expected %s" % (U.shape, _shape(c)))
+    return U
+
+
+def rhs(c: OCfg, U, allow_unphysical=False) -> np.ndarray:
+    U = _state(c, U)
+    L = np.empty_like(U)
+    rc = _load().oracle_rhs(ctypes.byref(c), _ptr(U), _ptr(L))
+    if not (allow_unphysical and rc == -4):
+        _check(rc)
+    return L
+
+
+def step(c: OCfg, U, dt: float) -> np.ndarray:
+    """One SSP-RK2 step with the given dt; returns the new state (copy)."""
+    U = _state(c, U).copy()
+    _check(_load().oracle_step(ctypes.byref(c), _ptr(U), float(dt)))
+    return U
+
+
+def dt(c: OCfg, U) -> float:
+    U = _state(c, U)
+    out = np.zeros(1)
+    _check(_load().oracle_dt(ctypes.byref(c), _ptr(U), _ptr(out)))
+    return float(out[0])
+
+
+def run(c: OCfg, U, nsteps: int):
+    """nsteps CFL-limited steps. Returns (new state, array of dts used)."""
+    U = _state(c, U).copy()
+    dts = np.zeros(max(nsteps, 1))
+    _check(_load().oracle_run(ctypes.byref(c), _ptr(U), int(nsteps), _ptr(dts)))
+    return U, dts[:nsteps]
+
+
+def run_dts(c: OCfg, U, dts) -> np.ndarray:
+    U = _state(c, U).copy()
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    _check(_load().oracle_run_dts(ctypes.byref(c), _ptr(U), len(d), _ptr(d)))
+    return U
+
+
+def step_jvp(c: OCfg, U, dU, dt: float, ddt: float = 0.0):
+    """Forward-mode tangent of one step: returns (Phi(U), dPhi.(dU, ddt))."""
+    U = _state(c, U).copy()
+    dU = _state(c, dU).copy()
+    _check(_load().oracle_step_jvp(ctypes.byref(c), _ptr(U), _ptr(dU), float(dt), float(ddt)))
+    return U, dU
+
+
+def divb(c: OCfg, U) -> np.ndarray:
+    U = _state(c, U)
+    out = np.empty(U.shape[1:])
+    _check(_load().oracle_divb(ctypes.byref(c), _ptr(U), _ptr(out)))
+    return out
+
+
+def prim(c: OCfg, U, allow_unphysical=False) -> np.ndarray:
+    U = _state(c, U)
+    V = np.empty_like(U)
+    rc = _load().oracle_prim(ctypes.byref(c), _ptr(U), _ptr(V))
+    if not (allow_unphysical and rc == -4):
+        _check(rc)
+    return V
+
+
+def riemann(wl, wr, bn, gamma=5.0 / 3.0, solver="hlld", precision="fp64") -> np.ndarray:
+    """Single face problem. w = (rho, u, v, w, B_t1, B_t2, p).
+    Returns 11 values: flux of (rho, m_n, m_t1, m_t2, B_t1, B_t2, E),
+    alpha+, alpha-, vt1, vt2."""
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    out = np.zeros(11)
+    _check(_load().oracle_riemann(SOLVERS[solver], PRECISIONS[precision], float(gamma),
+                                  _ptr(wl), _ptr(wr), float(bn), _ptr(out)))
+    return out
+
+
+def flux(w, bn, gamma=5.0 / 3.0):
+    """Physical flux of one face-frame primitive state: returns (U7, F7)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    U7 = np.zeros(7)
+    F7 = np.zeros(7)
+    _check(_load().oracle_flux(float(gamma), _ptr(w), float(bn), _ptr(U7), _ptr(F7)))
+    return U7, F7
+
+
+def slope(limiter: str, dm: float, dp: float) -> float:
+    return float(_load().oracle_slope(LIMITERS[limiter], float(dm), float(dp)))
+
+
+def fast_speed(gamma, rho, p, bn, bt1, bt2) -> float:
+    return float(_load().oracle_fast_speed(gamma, rho, p, bn, bt1, bt2))
+
+
+def uct(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN) -> float:
+    a = np.array([apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN], dtype=np.float64)
+    return float(_load().oracle_uct(_ptr(a)))

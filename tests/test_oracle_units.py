@@ -1,0 +1,279 @@
+"""Pins of the oracle's local pieces against what the mathematics fixes:
+closed forms, special cases with known exact answers, and invariants.
+
+Oracle functions covered: limited_slope, fast_speed, state_of (physical flux),
+riemann (HLL and HLLD), uct_emf, primitive recovery, CFL time step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2511_20337_amd import workloads as W
+
+G53 = 5.0 / 3.0
+
+
+# ---------------------------------------------------------------- limiter --
+@pytest.mark.parametrize("lim", ["minmod", "vanleer"])
+def test_slope_reproduces_linear_data(lim):
+    for d in (-2.5, -1e-7, 0.3, 7.0):
+        assert O.slope(lim, d, d) == pytest.approx(d, rel=2e-16)
+
+
+def test_slope_hand_values():
+    # minmod picks the smaller magnitude; zero at extrema
+    assert O.slope("minmod", 1.0, 2.0) == 1.0
+    assert O.slope("minmod", -3.0, -1.0) == -1.0
+    assert O.slope("minmod", 1.0, -1.0) == 0.0
+    assert O.slope("minmod", 0.0, 5.0) == 0.0
+    # van Leer harmonic mean 2ab/(a+b)
+    assert O.slope("vanleer", 1.0, 3.0) == 1.5
+    assert O.slope("vanleer", -2.0, -6.0) == -3.0
+    assert O.slope("vanleer", 2.0, -1.0) == 0.0
+
+
+@pytest.mark.parametrize("lim", ["minmod", "vanleer"])
+def test_slope_keeps_face_values_bounded(lim):
+    rng = np.random.default_rng(0)
+    for _ in range(2000):
+        a, b, c = rng.normal(size=3)
+        s = O.slope(lim, b - a, c - b)
+        lo, hi = min(a, b, c), max(a, b, c)
+        for f in (b + 0.5 * s, b - 0.5 * s):
+            assert lo - 1e-15 <= f <= hi + 1e-15
+        assert O.slope(lim, -(b - a), -(c - b)) == -s  # odd symmetry
+
+
+# ------------------------------------------------------------ fast speed --
+def test_fast_speed_closed_forms():
+    rho, p = 1.7, 0.9
+    cs = math.sqrt(G53 * p / rho)
+    assert O.fast_speed(G53, rho, p, 0, 0, 0) == pytest.approx(cs, rel=1e-15)
+    # field along the normal only: max(sound, Alfven)
+    for bn in (0.3, 2.0):
+        ca = abs(bn) / math.sqrt(rho)
+        assert O.fast_speed(G53, rho, p, bn, 0, 0) == pytest.approx(max(cs, ca), rel=1e-14)
+    # purely transverse field: sqrt(cs^2 + B^2/rho)
+    bt1, bt2 = 0.6, -0.8
+    want = math.sqrt(cs * cs + (bt1 ** 2 + bt2 ** 2) / rho)
+    assert O.fast_speed(G53, rho, p, 0, bt1, bt2) == pytest.approx(want, rel=1e-14)
+
+
+# --------------------------------------------------------- physical flux --
+def _tensor_flux(w, bn, g):
+    """Row of the flux tensor of Eq. (mhd) along the x normal, built from
+    full 3-vectors and outer products."""
+    rho, u, v, ww, b1, b2, p = w
+    vel = np.array([u, v, ww])
+    B = np.array([bn, b1, b2])
+    pt = p + 0.5 * B @ B
+    E = p / (g - 1) + 0.5 * rho * vel @ vel + 0.5 * B @ B
+    n = np.array([1.0, 0.0, 0.0])
+    mom = rho * np.outer(vel, vel) - np.outer(B, B) + pt * np.eye(3)
+    ind = np.outer(vel, B) - np.outer(B, vel)
+    en = (E + pt) * vel - (vel @ B) * B
+    return np.array([rho * vel @ n, *(n @ mom), *(n @ ind)[1:], en @ n]), E
+
+
+def test_physical_flux_matches_tensor_form():
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        w = np.array([rng.uniform(0.2, 3), *rng.normal(size=3), *rng.normal(size=2),
+                      rng.uniform(0.1, 2)])
+        bn = rng.normal()
+        U7, F7 = O.flux(w, bn)
+        Ft, E = _tensor_flux(w, bn, G53)
+        np.testing.assert_allclose(F7, Ft, rtol=1e-13, atol=1e-13)
+        assert U7[6] == pytest.approx(E, rel=1e-14)
+
+
+# ------------------------------------------------------------- Riemann ----
+def _rand_state(rng):
+    return np.array([rng.uniform(0.3, 2.0), *rng.normal(size=3), *rng.normal(size=2),
+                     rng.uniform(0.2, 2.0)])
+
+
+@pytest.mark.parametrize("solver", ["hll", "hlld"])
+def test_riemann_consistency(solver):
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        w = _rand_state(rng)
+        bn = rng.normal()
+        out = O.riemann(w, w, bn, solver=solver)
+        _, F = O.flux(w, bn)
+        np.testing.assert_allclose(out[:7], F, rtol=1e-13, atol=1e-13)
+        # with equal states the weighted transverse velocities are the states'
+        assert out[9] == pytest.approx(w[2], rel=1e-14, abs=1e-15)
+        assert out[10] == pytest.approx(w[3], rel=1e-14, abs=1e-15)
+
+
+@pytest.mark.parametrize("solver", ["hll", "hlld"])
+def test_riemann_supersonic_upwinding(solver):
+    # all waves to the right: the flux is the left physical flux
+    wl = np.array([1.0, 8.0, 0.1, -0.2, 0.3, 0.1, 0.5])
+    wr = np.array([0.7, 7.5, 0.0, 0.3, -0.2, 0.4, 0.4])
+    out = O.riemann(wl, wr, 0.4, solver=solver)
+    np.testing.assert_array_equal(out[:7], O.flux(wl, 0.4)[1])
+    assert out[8] == 0.0 and out[9] == pytest.approx(wl[2], rel=1e-15)
+    # mirror: all waves to the left
+    out = O.riemann(wr * [1, -1, 1, 1, 1, 1, 1], wl * [1, -1, 1, 1, 1, 1, 1], 0.4, solver=solver)
+    np.testing.assert_array_equal(out[:7], O.flux(wl * [1, -1, 1, 1, 1, 1, 1], 0.4)[1])
+
+
+@pytest.mark.parametrize("solver", ["hll", "hlld"])
+def test_riemann_mirror_symmetry(solver):
+    """Reflecting the normal axis (u -> -u, B_n -> -B_n, L <-> R) reflects the
+    flux: P = diag(-1, +1, -1, -1, -1, -1, -1)."""
+    rng = np.random.default_rng(3)
+    M = np.array([1, -1, 1, 1, 1, 1, 1.0])
+    P = np.array([-1, 1, -1, -1, -1, -1, -1.0])
+    for _ in range(200):
+        wl, wr = _rand_state(rng), _rand_state(rng)
+        bn = rng.normal()
+        a = O.riemann(wl, wr, bn, solver=solver)
+        b = O.riemann(M * wr, M * wl, -bn, solver=solver)
+        np.testing.assert_allclose(b[:7], P * a[:7], rtol=1e-12, atol=1e-12)
+        assert b[7] == pytest.approx(a[8], rel=1e-14) and b[8] == pytest.approx(a[7], rel=1e-14)
+
+
+def test_hlld_resolves_stationary_contact():
+    # u = 0, p and B continuous, B_n != 0, density jump: exact flux, F_L = F_R
+    bn = 0.7
+    wl = np.array([1.0, 0.0, 0.3, -0.2, 0.5, 0.25, 0.8])
+    wr = np.array([0.2, 0.0, 0.3, -0.2, 0.5, 0.25, 0.8])
+    out = O.riemann(wl, wr, bn, solver="hlld")
+    FL, FR = O.flux(wl, bn)[1], O.flux(wr, bn)[1]
+    np.testing.assert_allclose(FL, FR, atol=1e-15)
+    np.testing.assert_allclose(out[:7], FL, rtol=1e-13, atol=1e-14)
+    # HLL smears it: a nonzero mass flux appears
+    assert abs(O.riemann(wl, wr, bn, solver="hll")[0]) > 1e-3
+
+
+def test_hlld_resolves_stationary_rotational_discontinuity():
+    """A rotational discontinuity at rest in the frame of the face:
+    u = B_n/sqrt(rho) and v_t = B_t/sqrt(rho) on each side (same sign
+    convention), |B_t| equal, rho and p continuous. F_L = F_R (jump
+    conditions), and HLLD returns exactly that flux."""
+    rho, p, bn = 1.3, 0.6, 0.9
+    sq = math.sqrt(rho)
+    bt_l = np.array([0.8, 0.3])
+    ang = 1.9
+    R = np.array([[math.cos(ang), -math.sin(ang)], [math.sin(ang), math.cos(ang)]])
+    bt_r = R @ bt_l
+    wl = np.array([rho, bn / sq, bt_l[0] / sq, bt_l[1] / sq, bt_l[0], bt_l[1], p])
+    wr = np.array([rho, bn / sq, bt_r[0] / sq, bt_r[1] / sq, bt_r[0], bt_r[1], p])
+    FL, FR = O.flux(wl, bn)[1], O.flux(wr, bn)[1]
+    np.testing.assert_allclose(FL, FR, rtol=1e-13, atol=1e-13)
+    # shift to the frame where the discontinuity is at rest: u -> u - bn/sq
+    # means the wave moves at u - c_A = 0; here u = c_A so it is stationary.
+    out = O.riemann(wl, wr, bn, solver="hlld")
+    np.testing.assert_allclose(out[:7], FL, rtol=1e-12, atol=1e-12)
+
+
+def _hllc_b0(wl, wr, g):
+    """Three-wave HLLC flux of the Euler equations (transverse velocities
+    advected), with S_L, S_R as the MHD solver's at B = 0."""
+    def euler(w):
+        rho, u, v, ww, _, _, p = w
+        E = p / (g - 1) + 0.5 * rho * (u * u + v * v + ww * ww)
+        return (np.array([rho, rho * u, rho * v, rho * ww, 0, 0, E]),
+                np.array([rho * u, rho * u * u + p, rho * u * v, rho * u * ww, 0, 0, (E + p) * u]))
+    UL, FL = euler(wl)
+    UR, FR = euler(wr)
+    cl, cr = math.sqrt(g * wl[6] / wl[0]), math.sqrt(g * wr[6] / wr[0])
+    SL = min(wl[1], wr[1]) - max(cl, cr)
+    SR = max(wl[1], wr[1]) + max(cl, cr)
+    if SL > 0:
+        return FL
+    if SR < 0:
+        return FR
+    SM = (wr[6] - wl[6] + wl[0] * wl[1] * (SL - wl[1]) - wr[0] * wr[1] * (SR - wr[1])) / \
+        (wl[0] * (SL - wl[1]) - wr[0] * (SR - wr[1]))
+
+    def star(w, U, S):
+        rho, u, v, ww, _, _, p = w
+        f = rho * (S - u) / (S - SM)
+        return np.array([f, f * SM, f * v, f * ww, 0, 0,
+                         f * (U[6] / rho + (SM - u) * (SM + p / (rho * (S - u))))])
+    if SM >= 0:
+        return FL + SL * (star(wl, UL, SL) - UL)
+    return FR + SR * (star(wr, UR, SR) - UR)
+
+
+def test_hlld_reduces_to_hllc_without_field():
+    rng = np.random.default_rng(4)
+    for _ in range(300):
+        wl, wr = _rand_state(rng), _rand_state(rng)
+        wl[4:6] = 0.0
+        wr[4:6] = 0.0
+        out = O.riemann(wl, wr, 0.0, solver="hlld")
+        np.testing.assert_allclose(out[:7], _hllc_b0(wl, wr, G53), rtol=1e-11, atol=1e-12)
+
+
+def test_hlld_sod_limits():
+    """HLLD at B = 0 on the Sod states lies between the exact Godunov flux
+    and HLL in mass flux dissipation (a sanity bound)."""
+    wl = np.array([1.0, 0, 0, 0, 0, 0, 1.0])
+    wr = np.array([0.125, 0, 0, 0, 0, 0, 0.1])
+    d = O.riemann(wl, wr, 0.0, solver="hlld")
+    h = O.riemann(wl, wr, 0.0, solver="hll")
+    assert d[0] > 0 and h[0] > 0
+
+
+# --------------------------------------------------------------- UCT EMF --
+def test_uct_uniform_state_is_exact_emf():
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        va, vb, Ba, Bb = rng.normal(size=4)
+        apa, ama, apb, amb = rng.uniform(0.1, 3, size=4)
+        e = O.uct(apa, ama, va, Bb, va, Bb, apb, amb, vb, Ba, vb, Ba)
+        assert e == pytest.approx(vb * Ba - va * Bb, rel=1e-13, abs=1e-14)
+
+
+def test_uct_is_hll_flux_of_transverse_field():
+    """With identical S/N values the a-bracket is the HLL flux of B_b along a
+    with the W/E states: E = v_b B_a - HLL[v_a B_b]."""
+    rng = np.random.default_rng(6)
+    for _ in range(100):
+        vW, vE, bW, bE, vb, Ba = rng.normal(size=6)
+        SL, SR = -rng.uniform(0.1, 2), rng.uniform(0.1, 2)
+        ap, am = SR, -SL
+        e = O.uct(ap, am, vW, bW, vE, bE, 1.0, 1.0, vb, Ba, vb, Ba)
+        hll = (SR * vW * bW - SL * vE * bE + SL * SR * (bE - bW)) / (SR - SL)
+        assert e == pytest.approx(vb * Ba - hll, rel=1e-12, abs=1e-13)
+
+
+# ------------------------------------------------------ primitives / CFL --
+@pytest.mark.parametrize("dim", [2, 3])
+def test_primitive_round_trip(dim):
+    s, U = W.smooth_random(dim=dim, n=8, seed=11)
+    V = O.prim(O.cfg_from(s), U)
+    U2 = W.assemble(s, V[0], V[1], V[2], V[3], V[4], U[5], U[6], U[7])
+    np.testing.assert_allclose(U2, U, rtol=1e-14, atol=1e-14)
+
+
+def test_cfl_closed_form_uniform():
+    s, U = W.uniform(dim=3, n=8, v=(0.3, -0.5, 0.1), B=(0.4, 0.0, 0.0), p=0.7, rho=1.3)
+    c = O.cfg_from(s)
+    dx = 1.0 / 8
+    cs2 = G53 * 0.7 / 1.3
+    # x: field along the normal -> max(cs, ca); y,z: field transverse
+    cfx = max(math.sqrt(cs2), 0.4 / math.sqrt(1.3))
+    cft = math.sqrt(cs2 + 0.16 / 1.3)
+    want = 0.4 * min(dx / (0.3 + cfx), dx / (0.5 + cft), dx / (0.1 + cft))
+    assert O.dt(c, U) == pytest.approx(want, rel=1e-14)
+
+
+def test_unphysical_state_reported():
+    s, U = W.uniform(dim=2, n=8)
+    U = U.copy()
+    U[4, 0, 3, 3] = 0.01  # E below kinetic + magnetic energy: p < 0
+    c = O.cfg_from(s)
+    with pytest.raises(O.Unphysical):
+        O.dt(c, U)
+    with pytest.raises(O.Unphysical):
+        O.step(c, U, 1e-3)
+    with pytest.raises(O.OracleError):
+        O.step(c, U, -1.0)
