@@ -1,0 +1,155 @@
+/*
+ * mhd.h — C ABI of the MI355X (gfx950) ideal-MHD step library (libmhd.so).
+ *
+ * The library advances the conserved variables of ideal MHD,
+ *     dU/dt + div T(U) = 0,  U = (rho, rho v, B, E)              (paper Sec. 2.1,
+ *     E = p/(Gamma-1) + rho v^2/2 + B^2/2                        Eqs. cons_law, mhd, Energy)
+ * on a uniform, periodic Cartesian mesh with the semi-discrete finite-volume
+ * form of Sec. 2.2, Eq. (FV): primitive recovery (Sec. 2.2, inversion after
+ * Eq. reconstruct), piecewise-linear limited reconstruction (Eq. reconstruct),
+ * an HLLD or HLL Riemann flux at every interface (Sec. 2.2 flux equation;
+ * HLLD as cited for Secs. 4.1-4.2), an upwind constrained-transport EMF on
+ * cell edges that keeps div B at round-off (Sec. 2.2, CT), and a two-stage
+ * SSP Runge-Kutta step (Sec. 2.2, the SSP family of Eq. RK3).
+ *
+ * State layout (every call): one contiguous device buffer of 8*nz*ny*nx
+ * doubles, field-major, x fastest: element (f,k,j,i) at ((f*nz+k)*ny+j)*nx+i.
+ * Fields: 0 rho, 1 m_x, 2 m_y, 3 m_z, 4 E, 5 b_x, 6 b_y, 7 b_z. b_d is the
+ * normal field on the LOWER d-face of the cell (b_x(i) at x_{i-1/2}); the face
+ * at x_{-1/2} is the periodic image of x_{nx-1/2}. In 2D (nz == 1) field 7 is
+ * the cell-centred B_z.
+ *
+ * Ownership: the caller owns every device buffer (state, adjoint arrays and the
+ * workspace `ws` of `ws_bytes` >= mhd_workspace_bytes() bytes, 256-byte
+ * aligned; its contents need no initialisation except that the first 256
+ * bytes must be zero before the first call). The library allocates no
+ * device memory and keeps no device pointer between calls; a context holds
+ * host-side metadata only. Work is enqueued on the HIP stream given as
+ * `stream` (a hipStream_t; NULL = the default stream). Only calls that return
+ * a host value computed on the device (mhd_dt, mhd_check) synchronise.
+ * A context is used by one host thread at a time; calls on one workspace must
+ * not overlap.
+ *
+ * Errors: every call returns an mhd_status. MHD_ERR_DEVICE carries the HIP
+ * error text in mhd_last_error(). Kernels never abort: a cell with rho <= 0,
+ * p <= 0 or a non-finite value raises a sticky flag in the workspace that
+ * mhd_dt / mhd_check report as MHD_ERR_UNPHYSICAL (and clear). No floors are
+ * applied.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MHD_OK = 0,
+  MHD_ERR_INVALID = -1,      /* bad configuration, size, pointer or dt */
+  MHD_ERR_UNSUPPORTED = -2,  /* combination not built into this library */
+  MHD_ERR_DEVICE = -3,       /* HIP runtime / launch failure (see mhd_last_error) */
+  MHD_ERR_UNPHYSICAL = -4,   /* rho <= 0, p <= 0 or non-finite value met */
+  MHD_ERR_WORKSPACE = -5     /* workspace missing or too small */
+} mhd_status;
+
+typedef enum { MHD_LIM_MINMOD = 0, MHD_LIM_VANLEER = 1 } mhd_limiter;
+typedef enum { MHD_RS_HLLD = 0, MHD_RS_HLL = 1 } mhd_riemann;
+/* MHD_PREC_MIXED: reconstruction, Riemann solve and EMF in FP32; primitive
+ * recovery (incl. pressure), flux/curl differencing, the RK combination and
+ * the time step in FP64. The state is FP64 in both modes. */
+typedef enum { MHD_PREC_FP64 = 0, MHD_PREC_MIXED = 1 } mhd_precision;
+
+typedef struct {
+  int32_t dim;                  /* 2 or 3 */
+  int32_t nx, ny, nz;           /* cells per direction; nz == 1 when dim == 2; each >= 4 otherwise */
+  double xmin, xmax, ymin, ymax, zmin, zmax;  /* periodic box (max > min) */
+  double gamma;                 /* adiabatic index, > 1 */
+  double cfl;                   /* Courant number C > 0: dt = C min_d,cells dx_d/(|v_d|+c_f,d) */
+  int32_t limiter;              /* mhd_limiter */
+  int32_t riemann;              /* mhd_riemann */
+  int32_t precision;            /* mhd_precision */
+  int32_t reserved;             /* must be 0 */
+} mhd_config;
+
+typedef struct mhd_ctx mhd_ctx;
+
+/* Validate cfg and create a host-side context. No device work.
+ * Returns MHD_ERR_INVALID for a bad cfg or null out; *out is set on success. */
+mhd_status mhd_init(const mhd_config* cfg, mhd_ctx** out);
+
+/* Release a context (NULL is ignored). */
+void mhd_destroy(mhd_ctx* ctx);
+
+/* Bytes of device workspace the calls below need (with_adjoint != 0: enough
+ * for mhd_adjoint_step as well). 256-byte alignment is required. */
+size_t mhd_workspace_bytes(const mhd_ctx* ctx, int32_t with_adjoint);
+
+/* Time step of the state U (CFL condition; the paper gives no formula, see
+ * the design notes): dt = C min over cells and directions d of
+ * dx_d / (|v_d| + c_f,d), with c_f,d the fast magnetosonic speed along d.
+ * Writes the host double *dt_out; synchronises the stream. Reports (and
+ * clears) the unphysical flag as MHD_ERR_UNPHYSICAL, still writing dt. */
+mhd_status mhd_dt(mhd_ctx* ctx, const double* U, void* ws, size_t ws_bytes, double* dt_out,
+                  void* stream);
+
+/* Same time step, written to the device double *dt_dev; no synchronisation. */
+mhd_status mhd_dt_device(mhd_ctx* ctx, const double* U, void* ws, size_t ws_bytes, double* dt_dev,
+                         void* stream);
+
+/* One SSP-RK2 step of size dt, in place:
+ *   U1 = U + dt L(U);  U <- (U + (U1 + dt L(U1))) / 2,
+ * with L the finite-volume right-hand side (Eq. FV) for the cell fields and
+ * -curl E on the faces for the staggered field. dt must be > 0 and finite. */
+mhd_status mhd_step(mhd_ctx* ctx, double* U, double dt, void* ws, size_t ws_bytes, void* stream);
+
+/* As mhd_step with dt read on the device from *dt_dev (a device double, e.g.
+ * written by mhd_dt_device); no host synchronisation. */
+mhd_status mhd_step_device_dt(mhd_ctx* ctx, double* U, const double* dt_dev, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Right-hand side L(U) of the semi-discrete equations for all eight stored
+ * fields (same layout as U), without time integration. U and L must not
+ * alias. */
+mhd_status mhd_rhs(mhd_ctx* ctx, const double* U, double* L, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* Adjoint (vector-Jacobian product) of one mhd_step of size dt at the state
+ * U_n (left unchanged): Ubar_n = (dPhi/dU_n)^T Ubar_np1 and, if dtbar is
+ * non-NULL, the host double *dtbar = (dPhi/d dt)^T Ubar_np1 (this one
+ * synchronises). Not part of the paper: the derivative of every
+ * non-smooth point (limiter at extrema, min/max, Riemann region switches) is
+ * that of the branch the forward step takes. FP64 only. Ubar_n must not
+ * alias Ubar_np1 or U_n. Needs mhd_workspace_bytes(ctx, 1). */
+mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const double* Ubar_np1,
+                            double* Ubar_n, double* dtbar, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Synchronise the stream and report (and clear) the unphysical flag. */
+mhd_status mhd_check(mhd_ctx* ctx, void* ws, size_t ws_bytes, void* stream);
+
+/* Measurement support (not part of the method): enable != 0 turns on
+ * per-kernel timing for this context — every kernel launch of later calls is
+ * bracketed by a pair of HIP events on the call's stream — and resets the
+ * totals; enable == 0 turns it off. */
+mhd_status mhd_timing(mhd_ctx* ctx, int32_t enable);
+
+/* Read the timing totals of kernel index `kernel` (0, 1, ... until
+ * MHD_ERR_INVALID): its name, the summed event time in ms and the number of
+ * launches. Waits for the recorded events (synchronises). */
+mhd_status mhd_timing_read(mhd_ctx* ctx, int32_t kernel, const char** name, double* total_ms,
+                           int64_t* launches);
+
+/* Static text of a status code. */
+const char* mhd_strerror(mhd_status s);
+
+/* Text of the last failure on this context ("" if none). */
+const char* mhd_last_error(const mhd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHD_H */

@@ -1,0 +1,60 @@
+// Host-side launch interface between the C ABI and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mhd_device.hpp"
+
+namespace mhd {
+
+// Kernel identities for the optional per-kernel event timing.
+enum KernelId : int { K_FACES = 0, K_EMF, K_UPDATE, K_CFL, K_CFL_FINAL, K_ADJ, K_COUNT };
+
+// Records a pair of HIP events around each launch on the launch stream.
+struct Timer {
+  virtual void begin(int kid, hipStream_t s) = 0;
+  virtual void end(int kid, hipStream_t s) = 0;
+  virtual ~Timer() = default;
+};
+
+// One RK stage (or the bare right-hand side).
+struct StageArgs {
+  int dim, limiter, riemann, precision;
+  int stage;              // 0: out = L(U); 1: out = U + dt L; 2: out = (U0 + U + dt L)/2
+  Geom g;
+  const double* U;        // state the right-hand side is evaluated at
+  const double* U0;       // stage 2: state at the start of the step
+  double* out;
+  double* FW;             // face records: dim * NSLOT * n doubles
+  double* EW;             // edge EMFs: 3 * n doubles
+  double dt;
+  const double* dtp;      // device dt (nullptr: use dt)
+  int* flag;              // sticky unphysical flag
+  hipStream_t stream;
+  Timer* timer;           // nullable
+};
+
+struct CflArgs {
+  int dim;
+  Geom g;
+  const double* U;
+  double* partial;        // nblocks doubles
+  int nblocks;
+  double cfl;
+  double* dt_out;         // device double
+  int* flag;
+  hipStream_t stream;
+  Timer* timer;           // nullable
+};
+
+#define MHD_TIMED(args, kid, ...)                              \
+  do {                                                         \
+    if ((args).timer) (args).timer->begin((kid), (args).stream); \
+    __VA_ARGS__;                                               \
+    if ((args).timer) (args).timer->end((kid), (args).stream);   \
+  } while (0)
+
+hipError_t launch_stage(const StageArgs& a);
+hipError_t launch_cfl(const CflArgs& a);
+
+}  // namespace mhd

@@ -125,13 +125,22 @@ def band_modes(seed, kmin=1.0, kmax=4.0, solenoidal=True):
 
 def band_sample(K, C, n, offset, comp):
     """Re sum_k C_k exp(2 pi i k.x) at x = (index + offset) / n on an n^3 grid.
-    offset = (ox, oy, oz) in cells; returns array (n, n, n) in (z, y, x) order."""
-    spec = np.zeros((n, n, n), dtype=np.complex128)
-    ph = np.exp(2j * np.pi * (K[:, 0] * offset[0] + K[:, 1] * offset[1] +
-                              K[:, 2] * offset[2]) / n)
-    Ki = K.astype(np.int64) % n
-    np.add.at(spec, (Ki[:, 2], Ki[:, 1], Ki[:, 0]), C[:, comp] * ph)
-    return np.real(np.fft.ifftn(spec)) * float(n) ** 3
+    offset = (ox, oy, oz) in cells; returns array (n, n, n) in (z, y, x) order.
+    Evaluated as a separable contraction over the (small) band of modes."""
+    kk = int(np.abs(K).max())
+    m = 2 * kk + 1
+    dense = np.zeros((m, m, m), dtype=np.complex128)  # [kz, ky, kx]
+    Ki = K.astype(np.int64) + kk
+    np.add.at(dense, (Ki[:, 2], Ki[:, 1], Ki[:, 0]), C[:, comp])
+    ks = np.arange(-kk, kk + 1)[:, None]
+    idx = np.arange(n)[None, :]
+    ex = np.exp(2j * np.pi * ks * (idx + offset[0]) / n)  # [kx, x]
+    ey = np.exp(2j * np.pi * ks * (idx + offset[1]) / n)  # [ky, y]
+    ez = np.exp(2j * np.pi * ks * (idx + offset[2]) / n)  # [kz, z]
+    t1 = np.einsum("abc,cx->abx", dense, ex)               # [kz, ky, x]
+    t2 = np.einsum("abx,by->ayx", t1, ey).reshape(m, n * n)  # [kz, y*x]
+    out = ez.real.T @ t2.real - ez.imag.T @ t2.imag        # real part, [z, y*x]
+    return out.reshape(n, n, n)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,54 @@
+"""Host-only checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol include/mhd.h declares, and validates configurations."""
+import os
+import re
+
+import pytest
+
+from paper_2511_20337_amd import mhd, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_header_symbols_match_binding():
+    with open(os.path.join(ROOT, "include", "mhd.h")) as f:
+        src = f.read()
+    declared = set(re.findall(r"^\s*(?:mhd_status|void|size_t|const char\*)\s+(mhd_\w+)\s*\(",
+                              src, re.M))
+    assert declared == set(mhd.SYMBOLS)
+
+
+def test_library_exports_every_symbol():
+    L = mhd.lib()
+    for name in mhd.SYMBOLS:
+        assert hasattr(L, name), name
+
+
+def test_init_validates_config():
+    s, _ = W.turbulence_3d(8)
+    ctx = mhd.mhd_init(mhd.config_from(s))
+    n = 8 ** 3
+    fwd = mhd.mhd_workspace_bytes(ctx)
+    assert fwd >= 8 * 8 * n  # at least the stage-1 state
+    assert mhd.mhd_workspace_bytes(ctx, True) >= fwd
+    mhd.mhd_destroy(ctx)
+    bad = [("dim", 4), ("nx", 3), ("nz", 2), ("gamma", 1.0), ("cfl", 0.0), ("cfl", float("nan")),
+           ("xmax", 0.0), ("limiter", 2), ("riemann", -1), ("precision", 3), ("reserved", 1)]
+    for field, value in bad:
+        cfg = mhd.config_from(s)
+        setattr(cfg, field, value)
+        with pytest.raises(mhd.MHDError) as e:
+            mhd.mhd_init(cfg)
+        assert e.value.status == mhd.MHD_ERR_INVALID, field
+    s2, _ = W.orszag_tang_2d(8)
+    cfg = mhd.config_from(s2)
+    cfg.nz = 4  # 2D needs nz == 1
+    with pytest.raises(mhd.MHDError):
+        mhd.mhd_init(cfg)
+    mhd.mhd_destroy(mhd.mhd_init(mhd.config_from(s2)))
+
+
+def test_strerror_texts():
+    assert mhd.strerror(0) == "ok"
+    assert "unphysical" in mhd.strerror(-4)
+    assert "workspace" in mhd.strerror(-5)

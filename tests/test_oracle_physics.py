@@ -276,3 +276,19 @@ def test_mixed_precision_close_to_fp64():
         assert err < 1e-5, (q, err)
     # div B untouched: still a pure FP64 curl update
     assert np.abs(O.divb(cmx, Umx)).max() / np.abs(Umx[5:]).max() / 16 < 1e-12
+
+
+def test_patch_sampling_reproduces_full_grid():
+    """The sampled-cell oracle used for full-size GPU checks equals the oracle
+    on the whole grid, bit for bit, over two steps."""
+    from tests.oracle_patches import oracle_at_samples
+    s, U0 = W.turbulence_3d(32)
+    c = O.cfg_from(s)
+    d0 = O.dt(c, U0)
+    U1 = O.step(c, U0, d0)
+    d1 = O.dt(c, U1)
+    U2 = O.step(c, U1, d1)
+    cen = [(0, 0, 0), (31, 31, 31), (5, 17, 2), (16, 0, 30)]
+    r = oracle_at_samples(s, U0, [d0, d1], cen)
+    for n, (k, j, i) in enumerate(cen):
+        np.testing.assert_array_equal(r[n], U2[:, k, j, i])
