@@ -220,6 +220,10 @@ template <class R> R fast_speed(R g, R rho, R p, R bn, R bt1, R bt2) {
   return Sqrt((a + Sqrt(disc)) / (R(2) * rho));
 }
 
+// Relative tolerance of the HLLD degeneracy test, per working precision.
+template <class R> struct DegTol { static constexpr double value = 1e-12; };
+template <> struct DegTol<float> { static constexpr double value = 1e-12 * 536870912.0; };
+
 template <class R>
 void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
   R UL[7], FL[7], UR[7], FR[7], ptl, ptr;
@@ -272,8 +276,10 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
     rhos[s] = w[0] * su / sm;
     const R big = w[0] * su * sm;
     const R D = big - bn * bn;
-    // [reading] degenerate case (S_alpha ~ S*_alpha): tangential fields unchanged
-    if (Abs(D) <= R(1e-12) * (Abs(big) + bn * bn)) {
+    // [reading] degenerate case (S_alpha ~ S*_alpha): tangential fields
+    // unchanged when |D| is within a relative tolerance of 1e-12 in FP64
+    // units, scaled to the working precision (x 2^29 in FP32)
+    if (Abs(D) <= R(DegTol<R>::value) * (Abs(big) + bn * bn)) {
       vs[s] = w[2]; ws[s] = w[3]; b1s[s] = w[4]; b2s[s] = w[5];
     } else {
       const R fv = bn * (SM - w[1]) / D;

@@ -30,6 +30,9 @@ struct EventTimer final : mhd::Timer {
   double ms[mhd::K_COUNT] = {};
   int64_t count[mhd::K_COUNT] = {};
 
+  void note(hipError_t r) {
+    if (r != hipSuccess) err = r;
+  }
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -43,12 +46,12 @@ struct EventTimer final : mhd::Timer {
   }
   void begin(int kid, hipStream_t s) override {
     open_[kid] = get();
-    if (open_[kid]) hipEventRecord(open_[kid], s);
+    if (open_[kid]) note(hipEventRecord(open_[kid], s));
   }
   void end(int kid, hipStream_t s) override {
     hipEvent_t b = get();
     if (b && open_[kid]) {
-      hipEventRecord(b, s);
+      note(hipEventRecord(b, s));
       recs.push_back({kid, open_[kid], b});
     }
     open_[kid] = nullptr;
@@ -76,10 +79,10 @@ struct EventTimer final : mhd::Timer {
   }
   ~EventTimer() override {
     for (Rec& r : recs) {
-      hipEventDestroy(r.a);
-      hipEventDestroy(r.b);
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
     }
-    for (hipEvent_t e : pool) hipEventDestroy(e);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
 

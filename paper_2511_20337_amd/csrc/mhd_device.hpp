@@ -85,12 +85,19 @@ __device__ __forceinline__ void phys(R g, const R* w, R bn, R* u, R* f, R& pt) {
   f[6] = (en + pt) * vn - bn * vb;
 }
 
+// Relative tolerance below which the HLLD star state is treated as
+// degenerate: 1e-12 in FP64; the same number of units of the working
+// precision in FP32 (1e-12 * 2^29), where D = rho (S-u)(S-S_M) - bn^2 is
+// the small difference of two large terms at low plasma beta.
+template <class R> struct DegenerateTol { static constexpr double value = 1e-12; };
+template <> struct DegenerateTol<float> { static constexpr double value = 1e-12 * 536870912.0; };
+
 // HLL (RS 1) or HLLD (RS 0) flux between face-frame states wl | wr with
 // continuous normal field bn. Wave-speed bounds: S_L = min(u_L,u_R) - c,
 // S_R = max(u_L,u_R) + c, c = max(c_f,L, c_f,R). HLLD: the four-state solver
 // of Miyoshi & Kusano (contact S_M, Alfven fronts S*_L, S*_R); when
-// rho (S-u)(S-S_M) - bn^2 vanishes (relative 1e-12) the tangential fields of
-// that side's star state are left unchanged. Region ties go left.
+// rho (S-u)(S-S_M) - bn^2 vanishes (relative DegenerateTol) the tangential
+// fields of that side's star state are left unchanged. Region ties go left.
 template <int RS, class R>
 __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, RiemannOut<R>& o) {
   R ul[7], fl[7], ur[7], fr[7], ptl, ptr;
@@ -153,7 +160,7 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
     rs[s] = m * ism;
     const R big = m * (S - sm);
     const R den = big - bn2;
-    if (abs_r(den) <= R(1e-12) * (abs_r(big) + bn2)) {
+    if (abs_r(den) <= R(DegenerateTol<R>::value) * (abs_r(big) + bn2)) {
       vs[s] = w[2]; ws[s] = w[3]; b1s[s] = w[4]; b2s[s] = w[5];
     } else {
       const R iden2 = R(1) / den;

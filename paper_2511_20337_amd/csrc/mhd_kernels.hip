@@ -13,58 +13,12 @@
 // Layout: state and workspace arrays are field-major SoA, x fastest, so a
 // wavefront of 64 consecutive cells reads 512 contiguous bytes per field.
 #include "mhd_device.hpp"
+#include "mhd_grid.hpp"
 #include "mhd_kernels.hpp"
 
 namespace mhd {
 
 namespace {
-
-constexpr int kBlock = 256;
-
-__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-__device__ __forceinline__ int64_t lin(const Geom& g, int i, int j, int k) {
-  return ((int64_t)k * g.ny + j) * g.nx + i;
-}
-
-__device__ __forceinline__ void coords(const Geom& g, int64_t c, int& i, int& j, int& k) {
-  i = (int)(c % g.nx);
-  const int64_t r = c / g.nx;
-  j = (int)(r % g.ny);
-  k = (int)(r / g.ny);
-}
-
-// Cell shifted by s (|s| <= 2) along direction D, periodic.
-template <int D>
-__device__ __forceinline__ int64_t shifted(const Geom& g, int i, int j, int k, int s) {
-  if (D == 0) return lin(g, wrap(i + s, g.nx), j, k);
-  if (D == 1) return lin(g, i, wrap(j + s, g.ny), k);
-  return lin(g, i, j, wrap(k + s, g.nz));
-}
-
-// Primitive recovery at cell (i,j,k) (always FP64):
-// V = (rho, vx, vy, vz, p, Bx, By, Bz), B cell-centred as the mean of the two
-// faces (2D: field 7 is already cell-centred). Returns false for an
-// unphysical cell.
-template <int DIM>
-__device__ __forceinline__ bool prim_at(const double* __restrict__ U, const Geom& g, int i, int j,
-                                        int k, double* V) {
-  const int64_t n = g.n;
-  const int64_t c = lin(g, i, j, k);
-  const double rho = U[c];
-  const double mx = U[n + c], my = U[2 * n + c], mz = U[3 * n + c], en = U[4 * n + c];
-  const double bx = 0.5 * (U[5 * n + c] + U[5 * n + lin(g, wrap(i + 1, g.nx), j, k)]);
-  const double by = 0.5 * (U[6 * n + c] + U[6 * n + lin(g, i, wrap(j + 1, g.ny), k)]);
-  const double bz = (DIM == 3) ? 0.5 * (U[7 * n + c] + U[7 * n + lin(g, i, j, wrap(k + 1, g.nz))])
-                               : U[7 * n + c];
-  const double vx = mx / rho, vy = my / rho, vz = mz / rho;
-  const double kin = 0.5 * (mx * vx + my * vy + mz * vz);
-  const double mag = 0.5 * (bx * bx + by * by + bz * bz);
-  const double p = (g.gamma - 1.0) * (en - kin - mag);
-  V[0] = rho; V[1] = vx; V[2] = vy; V[3] = vz; V[4] = p; V[5] = bx; V[6] = by; V[7] = bz;
-  return (rho > 0.0) && (p > 0.0) && __builtin_isfinite(p) && __builtin_isfinite(vx) &&
-         __builtin_isfinite(vy) && __builtin_isfinite(vz);
-}
 
 // One lower face of direction D at cell (i,j,k): PLM from the four cells
 // c-2, c-1, c, c+1 along D (V0 is cell c), then the Riemann solve.
@@ -290,6 +244,8 @@ hipError_t stage_impl(const StageArgs& a) {
             hipLaunchKernelGGL((k_emf<DIM, LIM, R>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,
                                a.FW, a.EW, a.g));
   switch (a.stage) {
+    case 3:  // face and edge records only
+      break;
     case 0:
       MHD_TIMED(a, K_UPDATE,
                 hipLaunchKernelGGL((k_update<DIM, 0>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,

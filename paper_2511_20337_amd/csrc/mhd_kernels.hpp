@@ -20,7 +20,8 @@ struct Timer {
 // One RK stage (or the bare right-hand side).
 struct StageArgs {
   int dim, limiter, riemann, precision;
-  int stage;              // 0: out = L(U); 1: out = U + dt L; 2: out = (U0 + U + dt L)/2
+  int stage;              // 0: out = L(U); 1: out = U + dt L; 2: out = (U0 + U + dt L)/2;
+                          // 3: face/edge records only
   Geom g;
   const double* U;        // state the right-hand side is evaluated at
   const double* U0;       // stage 2: state at the start of the step

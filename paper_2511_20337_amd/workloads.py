@@ -395,6 +395,43 @@ def smooth_random(dim=3, n=16, seed=7, amp=0.05, limiter="vanleer", riemann="hll
     return s, assemble(s, rho, vx, vy, vz, p, bx + Bmean[0], by + Bmean[1], bz)
 
 
+def generic_state(dim, nx, ny, nz, limiter="vanleer", riemann="hlld", seed=1, cfl=0.3,
+                  gamma=5.0 / 3.0):
+    """Magnetised state on any (ragged) grid with no symmetry: each field is a
+    sum of two oblique modes plus seeded cell noise, and the staggered field
+    is the discrete curl of such a potential. No two faces or cells hold
+    bit-identical values, so the step has no tie in a limiter or min/max at
+    this state (such ties are kinks, where directional derivatives are not
+    linear)."""
+    s = make_setup("generic", dim, nx, ny, nz if dim == 3 else 1, (0, 1, 0, 1, 0, 1), gamma,
+                   cfl, limiter, riemann)
+    x, y, z = centres(s)
+    sh = (s["nz"], ny, nx)
+    rng = np.random.default_rng(seed)
+    tp = 2 * np.pi
+
+    def f():
+        out = np.zeros(sh)
+        for _ in range(2):
+            a, b, c = rng.integers(1, 3, 3) * rng.choice([-1, 1], 3)
+            out = out + np.sin(tp * (a * x + b * y + (c * z if dim == 3 else 0)) +
+                               rng.uniform(0, tp))
+        return out + 0.2 * rng.uniform(-1, 1, sh)
+    rho = 1.0 + 0.05 * f()
+    p = 0.6 + 0.05 * f()
+    vx, vy, vz = 0.3 + 0.1 * f(), -0.2 + 0.1 * f(), 0.1 + 0.1 * f()
+
+    def A():
+        return 0.03 * f() / tp
+    if dim == 2:
+        bx, by = curl_of_edge_potential(s, None, None, A())
+        bz = 0.2 + 0.05 * f()
+    else:
+        bx, by, bz = curl_of_edge_potential(s, A(), A(), A())
+        bz = bz - 0.15
+    return s, assemble(s, rho, vx, vy, vz, p, bx + 0.4, by + 0.25, bz)
+
+
 WORKLOADS = {
     "orszag_tang_2d": orszag_tang_2d,
     "turbulence_3d": turbulence_3d,

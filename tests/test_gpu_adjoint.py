@@ -1,0 +1,211 @@
+"""The HIP adjoint of one step (mhd_adjoint_step) against the oracle.
+
+The oracle's forward-mode tangent (a dual-number evaluation of its own step)
+gives exact Jacobian-vector products; the adjoint must satisfy
+(J^T ubar)_i = <ubar, J e_i> element by element on tiny grids, and
+<J^T ubar, delta> + dtbar ddt = <ubar, J delta + dPhi/ddt ddt> on larger ones.
+Multi-step gradients through the autograd wrapper are checked for checkpoint
+invariance and against central finite differences (frozen time steps).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2511_20337_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2511_20337_amd import mhd
+    mhd.lib()
+    return torch.device("cuda:0")
+
+
+def smooth_ragged(dim, nx, ny, nz, lim, solver, seed=1):
+    return W.generic_state(dim, nx, ny, nz, lim, solver, seed=seed)
+
+
+def gpu_adjoint(s, U, dt, ubar, dev):
+    from paper_2511_20337_amd import mhd
+    ctx = mhd.Context(s, dev, with_adjoint=True)
+    Ug = torch.from_numpy(U).to(dev)
+    ub = torch.from_numpy(ubar).to(dev)
+    out, dtbar = ctx.adjoint_step(Ug, dt, ub, want_dtbar=True)
+    torch.cuda.synchronize()
+    # the input state must be left unchanged
+    np.testing.assert_array_equal(Ug.cpu().numpy(), U)
+    return out.cpu().numpy(), dtbar
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("lim", ["minmod", "vanleer"])
+@pytest.mark.parametrize("solver", ["hlld", "hll"])
+def test_adjoint_elementwise(dev, dim, lim, solver):
+    if dim == 2:
+        s, U = smooth_ragged(2, 6, 5, 1, lim, solver)
+    else:
+        s, U = smooth_ragged(3, 5, 4, 4, lim, solver)
+    print("adjoint elementwise", dim, lim, solver, flush=True)
+    c = O.cfg_from(s)
+    dt = O.dt(c, U)
+    rng = np.random.default_rng(7)
+    ubar = rng.normal(size=U.shape)
+    got, dtbar = gpu_adjoint(s, U, dt, ubar, dev)
+    ref = np.zeros(U.size)
+    e = np.zeros(U.size)
+    for idx in range(U.size):
+        e[idx] = 1.0
+        _, jv = O.step_jvp(c, U, e.reshape(U.shape), dt)
+        ref[idx] = float((ubar * jv).sum())
+        e[idx] = 0.0
+    ref = ref.reshape(U.shape)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-11 * scale, np.abs(got - ref).max() / scale
+    _, jdt = O.step_jvp(c, U, np.zeros_like(U), dt, 1.0)
+    assert dtbar == pytest.approx(float((ubar * jdt).sum()), rel=1e-11, abs=1e-14)
+
+
+@pytest.mark.parametrize("case", ["2d_32", "3d_12", "3d_16_minmod_hll"])
+def test_adjoint_dot_product(dev, case):
+    if case == "2d_32":
+        s, U = smooth_ragged(2, 32, 28, 1, "vanleer", "hlld", seed=3)
+    elif case == "3d_12":
+        s, U = smooth_ragged(3, 12, 10, 11, "vanleer", "hlld", seed=4)
+    else:
+        s, U = smooth_ragged(3, 16, 16, 16, "minmod", "hll", seed=6)
+    c = O.cfg_from(s)
+    dt = O.dt(c, U)
+    rng = np.random.default_rng(11)
+    ubar = rng.normal(size=U.shape)
+    got, dtbar = gpu_adjoint(s, U, dt, ubar, dev)
+    for trial in range(3):
+        delta = rng.normal(size=U.shape)
+        ddt = rng.normal() * dt
+        _, jv = O.step_jvp(c, U, delta, dt, ddt)
+        lhs = float((got * delta).sum()) + dtbar * ddt
+        rhs = float((ubar * jv).sum())
+        assert lhs == pytest.approx(rhs, rel=1e-11), (trial, lhs, rhs)
+
+
+def test_adjoint_rejects_bad_arguments(dev):
+    from paper_2511_20337_amd import mhd
+    s, U = smooth_ragged(2, 8, 8, 1, "vanleer", "hlld")
+    ctx = mhd.Context(s, dev, with_adjoint=True)
+    Ug = torch.from_numpy(U).to(dev)
+    ub = torch.zeros_like(Ug)
+    with pytest.raises(mhd.MHDError) as e:
+        mhd.mhd_adjoint_step(ctx.ctx, Ug, 1e-3, ub, ub, ctx.ws)
+    assert e.value.status == mhd.MHD_ERR_INVALID
+    small = mhd.Context(s, dev)  # forward-only workspace
+    with pytest.raises(mhd.MHDError) as e:
+        small.adjoint_step(Ug, 1e-3, ub)
+    assert e.value.status == mhd.MHD_ERR_WORKSPACE
+    mixed = dict(s)
+    mixed["precision"] = "mixed"
+    cm = mhd.Context(mixed, dev, with_adjoint=True)
+    with pytest.raises(mhd.MHDError) as e:
+        cm.adjoint_step(Ug, 1e-3, ub)
+    assert e.value.status == mhd.MHD_ERR_UNSUPPORTED
+
+
+def test_multistep_gradient_checkpoint_invariant(dev):
+    """Gradients of a 10-step run through the autograd wrapper: identical for
+    checkpoint intervals 1, 3 and 10, and equal to a chain of oracle JVPs in
+    the dot-product sense."""
+    from paper_2511_20337_amd import adjoint as AD, mhd
+    s, U = smooth_ragged(2, 16, 12, 1, "vanleer", "hlld", seed=5)
+    ctx = mhd.Context(s, dev, with_adjoint=True)
+    U0 = torch.from_numpy(U).to(dev)
+    dts, _ = AD.record_dts(ctx, U0, 10)
+    rng = np.random.default_rng(2)
+    w = torch.from_numpy(rng.normal(size=U.shape)).to(dev)
+    grads = []
+    for every in (1, 3, 10):
+        x = U0.clone().requires_grad_(True)
+        d = dts.clone().requires_grad_(True)
+        out = AD.run_with_grad(ctx, x, d, every=every)
+        (out * w).sum().backward()
+        grads.append((x.grad.cpu().numpy(), d.grad.numpy()))
+    for g, gd in grads[1:]:
+        np.testing.assert_array_equal(g, grads[0][0])
+        np.testing.assert_array_equal(gd, grads[0][1])
+    # oracle: tangent through all steps along a random direction
+    c = O.cfg_from(s)
+    delta = rng.normal(size=U.shape)
+    ddts = rng.normal(size=10) * dts.numpy()
+    Uc, dU = U.copy(), delta.copy()
+    for k in range(10):
+        Uc, dU = O.step_jvp(c, Uc, dU, float(dts[k]), float(ddts[k]))
+    lhs = float((grads[0][0] * delta).sum() + (grads[0][1] * ddts).sum())
+    rhs = float((w.cpu().numpy() * dU).sum())
+    assert lhs == pytest.approx(rhs, rel=1e-10)
+
+
+def _kh_objective_seed(s, UN):
+    """J = dx dy sum_cells |B_c|^2 / 2 and its gradient w.r.t. the state."""
+    dx, dy, _ = W.spacing(s)
+    area = dx * dy
+    bx, by, bz = UN[5], UN[6], UN[7]
+    bcx = 0.5 * (bx + torch.roll(bx, -1, dims=2))
+    bcy = 0.5 * (by + torch.roll(by, -1, dims=1))
+    seed = torch.zeros_like(UN)
+    seed[5] = area * 0.5 * (bcx + torch.roll(bcx, 1, dims=2))
+    seed[6] = area * 0.5 * (bcy + torch.roll(bcy, 1, dims=1))
+    seed[7] = area * bz
+    return seed
+
+
+def _kh_delta_J(s, Ua, Ub):
+    """J(Ua) - J(Ub) without cancellation: sum of (a - b)(a + b)/2."""
+    dx, dy, _ = W.spacing(s)
+
+    def bc(U):
+        return (0.5 * (U[5] + torch.roll(U[5], -1, dims=2)),
+                0.5 * (U[6] + torch.roll(U[6], -1, dims=1)), U[7])
+    tot = 0.0
+    for a, b in zip(bc(Ua), bc(Ub)):
+        tot += float(((a - b) * (a + b)).sum()) * 0.5
+    return tot * dx * dy
+
+
+@pytest.mark.parametrize("n,nsteps", [(512, 64)])
+def test_kh_mode_gradient_vs_central_fd(dev, n, nsteps):
+    """Kelvin-Helmholtz: gradient of the magnetic energy after N steps w.r.t.
+    the 16 perturbation amplitudes, via the checkpointed adjoint (every 8
+    steps), against central differences with h = 1e-6 and the recorded time
+    steps frozen."""
+    from paper_2511_20337_amd import adjoint as AD, mhd
+    s, U, phases = W.kelvin_helmholtz_2d(n)
+    amps = np.full(16, 1e-2)
+    print("KH %d^2, %d steps" % (n, nsteps), flush=True)
+    ctx = mhd.Context(s, dev, with_adjoint=True)
+    U0 = torch.from_numpy(U).to(dev)
+    dts, _ = AD.record_dts(ctx, U0, nsteps)
+    x = U0.clone().requires_grad_(True)
+    UN = AD.run_with_grad(ctx, x, dts, every=8)
+    seed = _kh_objective_seed(s, UN.detach())
+    UN.backward(seed)
+    gbar = x.grad.cpu().numpy()
+    basis = W.kh_mode_basis(s, phases)
+    vy = U[2] / U[0]
+    grad = np.array([float(((gbar[2] * U[0] + gbar[4] * U[0] * vy) * b).sum()) for b in basis])
+    h = 1e-6
+    fd = np.zeros(16)
+    for m in range(16):
+        out = []
+        for sign in (1, -1):
+            a = amps.copy()
+            a[m] += sign * h
+            _, Um, _ = W.kelvin_helmholtz_2d(n, amps=a)
+            Ug = torch.from_numpy(Um).to(dev)
+            for dt in dts.tolist():
+                ctx.step(Ug, dt)
+            out.append(Ug)
+        fd[m] = _kh_delta_J(s, out[0], out[1]) / (2 * h)
+    err = np.abs(grad - fd).max() / np.abs(fd).max()
+    print("KH gradient vector-relative error vs FD: %.3e" % err, flush=True)
+    assert err <= 1e-6, (err, grad, fd)

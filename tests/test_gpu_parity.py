@@ -260,9 +260,11 @@ def test_mixed_precision_parity(dev):
     e_mx = rel_err(got, refmx)
     e_64 = rel_err(got, ref64)
     print("mixed vs oracle-mixed", e_mx, "\nmixed vs fp64", e_64, flush=True)
-    # two independent FP32 roundings differ by as much as FP32 from FP64 here
-    assert (e_mx <= 1e-3).all(), e_mx
-    assert (e_64 <= 1e-3).all(), e_64
+    # stated error of the mixed path on this workload (measured <= 2.6e-6 and
+    # <= 1.1e-5 per field)
+    assert (e_mx <= 2e-5).all(), e_mx
+    assert (e_64 <= 1e-4).all(), e_64
+    ctx.check()  # positivity kept
     div = O.divb(c64, got)
     assert np.abs(div).max() / 64 / np.abs(got[5:]).max() <= 1e-12
 
