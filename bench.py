@@ -36,20 +36,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes_per_cell(name: str, dim: int) -> float:
-    """Algorithmic HBM bytes per cell of one launch of each kernel, from what
-    the kernel must read and write once (halo re-reads excluded)."""
-    faces_out = dim * (5 if dim == 3 else 6) + dim * 4    # fluxes + alpha+- + 2 velocities
-    table = {
-        "faces": 8 * (8 + faces_out),                       # read U, write face records
-        "emf": 8 * (dim * 4 + dim + (3 if dim == 3 else 1)),  # read alpha,v, b; write E
-        "update": 8 * (faces_out - dim * 4 + (3 if dim == 3 else 1) + 8 + 8),  # fluxes, E, U, out
-        "cfl": 8 * 8,
-    }
-    return float(table.get(name, 0.0))
+# Algorithmic work of one launch of each forward kernel, per cell (3D):
+#  bytes: what the kernel must read and write once (halo re-reads excluded);
+#  flops: FP64 operations of the method's definition (add/sub, mul, div, sqrt
+#         each one), counted by oracle/count_flops.py on this workload.
+KERNEL_BYTES = {"faces": 8 * (8 + 27),          # read U, write 3 x 9 face values
+                "emf": 8 * (12 + 3 + 3),        # read alpha+-, 2 velocities per face, b; write E
+                "update": 8 * (15 + 3 + 8 + 8 + 8),  # fluxes, E, U, U0 (stage 2), write
+                "cfl": 8 * 8}
+KERNEL_FLOPS = {"faces": 1336.5, "emf": 277.7, "update": 55.0}
+KERNEL_BOUND = {"faces": "alu", "emf": "hbm", "update": "hbm", "cfl": "hbm"}
+# HBM bytes per cell of one launch measured with rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (scaled by the copy-kernel calibration, 2.0 and 1.0), for the
+# kernels as they stand; see profiles/.
+KERNEL_TRAFFIC = {"faces": 143.6 + 216.0}
 
 
 def time_gpu(setup, U0, steps, warmup, timing=True):
+    """Time `steps` whole steps (device dt + RK2 step) after `warmup` steps.
+    Returns (seconds, per-kernel event totals, final state, physical?)."""
     import torch
     from paper_2511_20337_amd import mhd
     dev = torch.device("cuda:0")
@@ -70,8 +75,35 @@ def time_gpu(setup, U0, steps, warmup, timing=True):
     kt = mhd.mhd_timing_read(ctx.ctx) if timing else {}
     if timing:
         mhd.mhd_timing(ctx.ctx, False)
-    ctx.check()
-    return elapsed, kt, U
+    try:
+        ctx.check()
+        physical = True
+    except mhd.Unphysical:
+        physical = False
+    return elapsed, kt, U, physical
+
+
+def time_adjoint(n, nsteps, every):
+    """Kelvin-Helmholtz n^2: N forward steps with checkpoints, then the
+    checkpointed backward (segment replay + adjoint steps). Returns adjoint
+    steps/s of the backward pass and the forward steps/s."""
+    import torch
+    from paper_2511_20337_amd import adjoint as AD, mhd, workloads as W
+    dev = torch.device("cuda:0")
+    s, U, _ = W.kelvin_helmholtz_2d(n)
+    ctx = mhd.Context(s, dev, with_adjoint=True)
+    U0 = torch.from_numpy(U).to(dev)
+    dts, _ = AD.record_dts(ctx, U0, nsteps)
+    x = U0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = AD.run_with_grad(ctx, x, dts, every=every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out.backward(torch.ones_like(out))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return nsteps / (t2 - t1), nsteps / (t1 - t0)
 
 
 def cpu_baseline(n_sample: int, setup_fn):
@@ -92,6 +124,23 @@ def cpu_baseline(n_sample: int, setup_fn):
                       "%d OpenMP threads" % (n_sample, el, threads)}
 
 
+def copy_probe(mib: int) -> int:
+    """A plain copy of known size, timed, as the reference for HBM counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "copies": 5, "GBps": 2 * n * 8 / el / 1e9}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,7 +149,14 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=256, help="grid cells per side")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128, help="oracle sample size per side")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision and adjoint measurements")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates the "
+                         "HBM byte counters) and exit")
     args = ap.parse_args(argv)
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -115,7 +171,7 @@ def main(argv=None):
     setup, U0 = make(args.n)
     ncell = args.n ** 3
     log("timing %d steps after %d warmup" % (args.steps, args.warmup))
-    elapsed, kt, _ = time_gpu(setup, U0, args.steps, args.warmup)
+    elapsed, kt, _, physical = time_gpu(setup, U0, args.steps, args.warmup)
     value = ncell * args.steps / elapsed / 1e6
     ms_per_step = elapsed / args.steps * 1e3
 
@@ -123,11 +179,21 @@ def main(argv=None):
     dom = max(kt.items(), key=lambda kv: kv[1][0])
     name, (tot_ms, launches) = dom
     avg_s = tot_ms / launches / 1e3
-    bpc = kernel_bytes_per_cell(name, 3)
-    achieved = bpc * ncell / avg_s
-    roofline = {"kernel": name, "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
-                "avg_launch_ms": avg_s * 1e3, "bytes_per_cell": bpc}
+    bound = KERNEL_BOUND.get(name, "hbm")
+    bpc = KERNEL_BYTES.get(name, 0)
+    traffic = KERNEL_TRAFFIC.get(name)
+    if bound == "alu":
+        achieved = KERNEL_FLOPS[name] * ncell / avg_s
+        roofline = {"kernel": name, "bound": "alu", "achieved": achieved / 1e12,
+                    "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK}
+    else:
+        achieved = bpc * ncell / avg_s
+        roofline = {"kernel": name, "bound": "hbm", "achieved": achieved / 1e9,
+                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK}
+    roofline.update({"traffic": traffic * ncell if traffic else None,
+                     "traffic_unit": "bytes per launch", "avg_launch_ms": avg_s * 1e3,
+                     "flops_per_cell": KERNEL_FLOPS.get(name), "bytes_per_cell": bpc,
+                     "hbm_algorithmic_GBps": bpc * ncell / avg_s / 1e9})
     kernels = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "share": v[0] / sum(x[0] for x in kt.values())}
                for k, v in kt.items() if v[1]}
 
@@ -148,9 +214,28 @@ def main(argv=None):
                    "limiter": "vanleer", "riemann": "hlld", "emf": "uct_hll",
                    "integrator": "ssp_rk2", "cfl": 0.3, "precision": "fp64"},
         "hbm_roofline_frac_step": value * 1e6 * STEP_BYTES / HBM_PEAK,
+        "physical": physical,
         "roofline": roofline,
         "kernels": kernels,
     }
+    if not args.no_extras:
+        del U0
+        log("mixed precision: low-beta turbulence %d^3" % args.n)
+        sm, Um = W.turbulence_3d_lowbeta(args.n)
+        el_m, kt_m, _, phys_m = time_gpu(sm, Um, args.steps, args.warmup)
+        del Um
+        vm = ncell * args.steps / el_m / 1e6
+        out["mixed"] = {"value": vm, "unit": "Mcell-updates/s", "ms_per_step": el_m / args.steps * 1e3,
+                        "hbm_roofline_frac_step": vm * 1e6 * STEP_BYTES / HBM_PEAK,
+                        "physical": phys_m,
+                        "config": {"workload": "turbulence_3d_lowbeta_%d" % args.n, "mach": 3,
+                                   "beta": 0.01, "precision": "mixed"},
+                        "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_m.items() if v[1]}}
+        log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, checkpoints every 8")
+        adj, fwd = time_adjoint(512, 64, 8)
+        out["adjoint"] = {"value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
+                          "config": {"workload": "kelvin_helmholtz_2d_512", "steps": 64,
+                                     "checkpoint_every": 8}}
     if not args.no_cpu:
         log("cpu baseline: oracle at %d^3" % args.cpu_n)
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, make)

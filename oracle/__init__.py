@@ -79,6 +79,7 @@ def _load():
             ("oracle_slope", [ctypes.c_int, ctypes.c_double, ctypes.c_double], ctypes.c_double),
             ("oracle_fast_speed", [ctypes.c_double] * 6, ctypes.c_double),
             ("oracle_uct", [dp], ctypes.c_double),
+            ("oracle_count_ops", [cp, dp, P(ctypes.c_longlong)], ctypes.c_int),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -224,3 +225,14 @@ def fast_speed(gamma, rho, p, bn, bt1, bt2) -> float:
 def uct(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN) -> float:
     a = np.array([apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN], dtype=np.float64)
     return float(_load().oracle_uct(_ptr(a)))
+
+
+def count_ops(c: OCfg, U) -> dict:
+    """Floating-point operations of one right-hand side per phase
+    (prims, faces, emf, update), each {add, mul, div, sqrt} totals."""
+    U = _state(c, U)
+    out = (ctypes.c_longlong * 16)()
+    _check(_load().oracle_count_ops(ctypes.byref(c), _ptr(U), out))
+    names = ("prims", "faces", "emf", "update")
+    kinds = ("add", "mul", "div", "sqrt")
+    return {names[p]: {kinds[k]: int(out[4 * p + k]) for k in range(4)} for p in range(4)}

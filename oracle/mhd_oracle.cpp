@@ -71,9 +71,33 @@ inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
 inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
 inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
 
+// Operation-counting scalar: the value of a double, and a count of every
+// floating-point operation (add/sub, mul, div, sqrt) charged to the current
+// phase of the right-hand side. Used only to state the algorithmic flops per
+// cell of each phase of the method.
+enum { PH_PRIM = 0, PH_FACE, PH_EMF, PH_UPDATE, PH_N };
+long long g_ops[PH_N][4];
+int g_phase = 0;
+struct Cnt {
+  double v;
+  Cnt() : v(0.0) {}
+  Cnt(double x) : v(x) {}  // NOLINT: implicit on purpose
+};
+inline Cnt cnt(double x, int kind) { g_ops[g_phase][kind] += 1; return Cnt(x); }
+inline Cnt operator+(Cnt a, Cnt b) { return cnt(a.v + b.v, 0); }
+inline Cnt operator-(Cnt a, Cnt b) { return cnt(a.v - b.v, 0); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt operator*(Cnt a, Cnt b) { return cnt(a.v * b.v, 1); }
+inline Cnt operator/(Cnt a, Cnt b) { return cnt(a.v / b.v, 2); }
+inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
+inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
+inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
+inline bool operator>=(Cnt a, Cnt b) { return a.v >= b.v; }
+
 inline double val(double x) { return x; }
 inline double val(float x) { return (double)x; }
 inline double val(Dual x) { return x.v; }
+inline double val(Cnt x) { return x.v; }
 
 inline double Sqrt(double x) { return std::sqrt(x); }
 inline float Sqrt(float x) { return std::sqrt(x); }
@@ -84,12 +108,15 @@ inline Dual Sqrt(Dual x) {
 inline double Abs(double x) { return std::fabs(x); }
 inline float Abs(float x) { return std::fabs(x); }
 inline Dual Abs(Dual x) { return x.v < 0.0 ? -x : x; }
+inline Cnt Sqrt(Cnt x) { return cnt(std::sqrt(x.v), 3); }
+inline Cnt Abs(Cnt x) { return Cnt(std::fabs(x.v)); }
 // min/max return the first argument on ties.
 template <class T> inline T Max(T a, T b) { return (b > a) ? b : a; }
 template <class T> inline T Min(T a, T b) { return (b < a) ? b : a; }
 inline bool Finite(double x) { return std::isfinite(x); }
 inline bool Finite(float x) { return std::isfinite(x); }
 inline bool Finite(Dual x) { return std::isfinite(x.v); }
+inline bool Finite(Cnt x) { return std::isfinite(x.v); }
 
 // Conversions between the state scalar and the face scalar.
 template <class To> struct Cast;
@@ -103,6 +130,9 @@ template <> struct Cast<float> {
 };
 template <> struct Cast<Dual> {
   static Dual of(Dual x) { return x; }
+};
+template <> struct Cast<Cnt> {
+  static Cnt of(Cnt x) { return x; }
 };
 
 // ---------------------------------------------------------------------------
@@ -373,6 +403,7 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
 
   auto F = [&](int f) { return U + (size_t)f * n; };
 
+  g_phase = PH_PRIM;
   // --- primitives (Sec. 2.2 primitive inversion), FP64 in every mode -------
   std::vector<S> V((size_t)NF * n);
   auto Vf = [&](int f) { return V.data() + (size_t)f * n; };
@@ -400,6 +431,7 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
   });
   for (int r : badk) bad |= r;
 
+  g_phase = PH_FACE;
   // --- per direction: reconstruction + Riemann solve at every lower face ---
   // Face arrays: flux of the eight stored components in the global frame
   // (promoted to S), alpha+-, and the HLL-weighted velocity (global comps).
@@ -449,6 +481,7 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
     });
   }
 
+  g_phase = PH_EMF;
   // --- upwind CT EMF on cell edges -----------------------------------------
   // Edge of component c stored at cell (i,j,k) sits at the lower a- and lower
   // b-position of that cell: E_z at (i-1/2, j-1/2, k), E_x at (i, j-1/2, k-1/2),
@@ -495,6 +528,7 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
     });
   }
 
+  g_phase = PH_UPDATE;
   // --- flux-divergence update of cell fields; curl update of face fields ---
   par_rows(G, cfg.nthreads, [&](int j, int k) {
       for (int i = 0; i < G.nx; ++i) {
@@ -675,6 +709,26 @@ int oracle_step_jvp(const OCfg* cfg, double* U, double* dU, double dt, double dd
     return compute_rhs<Dual, Dual>(c, u, l);
   });
   for (size_t q = 0; q < N; ++q) { U[q] = Ud[q].v; dU[q] = Ud[q].d; }
+  return bad ? -4 : 0;
+}
+
+// Floating-point operations of one right-hand side evaluation, single
+// threaded, per phase: out[4*phase + kind], kind = add/sub, mul, div, sqrt;
+// phases: primitives, faces (reconstruction + Riemann), EMF, update.
+int oracle_count_ops(const OCfg* cfg, const double* U, long long* out) {
+  if (!cfg_ok(cfg) || !U || !out) return -1;
+  OCfg c = *cfg;
+  c.nthreads = 1;
+  c.precision = 0;
+  const Grid G(c);
+  const size_t N = (size_t)NF * G.ncell;
+  std::vector<Cnt> Uc(N), Lc(N);
+  for (size_t q = 0; q < N; ++q) Uc[q] = Cnt(U[q]);
+  for (int p = 0; p < PH_N; ++p)
+    for (int k = 0; k < 4; ++k) g_ops[p][k] = 0;
+  int bad = compute_rhs<Cnt, Cnt>(c, Uc.data(), Lc.data());
+  for (int p = 0; p < PH_N; ++p)
+    for (int k = 0; k < 4; ++k) out[4 * p + k] = g_ops[p][k];
   return bad ? -4 : 0;
 }
 

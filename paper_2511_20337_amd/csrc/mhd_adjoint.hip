@@ -58,6 +58,8 @@ __device__ __forceinline__ Dual sqrt_r(Dual x) {
   return Dual(s, s > 0.0 ? 0.5 * x.d / s : 0.0);
 }
 __device__ __forceinline__ Dual abs_r(Dual x) { return x.v < 0.0 ? -x : x; }
+__device__ __forceinline__ Dual rcp_r(Dual x) { return Dual(1.0) / x; }
+__device__ __forceinline__ Dual div_r(Dual a, Dual b) { return a / b; }
 
 // Edge-partial slots: d E / d input times Ebar.
 enum : int { E_APA = 0, E_AMA, E_VW, E_BW, E_VE, E_BE, E_APB, E_AMB, E_VS, E_BS, E_VN, E_BN, NE };

@@ -8,7 +8,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/mhd.h"
+#include "mhd.h"
 #include "mhd_adjoint.hpp"
 #include "mhd_kernels.hpp"
 

@@ -43,7 +43,8 @@ __device__ __forceinline__ bool prim_at(const double* __restrict__ U, const Geom
   const double by = 0.5 * (U[6 * n + c] + U[6 * n + lin(g, i, wrap(j + 1, g.ny), k)]);
   const double bz = (DIM == 3) ? 0.5 * (U[7 * n + c] + U[7 * n + lin(g, i, j, wrap(k + 1, g.nz))])
                                : U[7 * n + c];
-  const double vx = mx / rho, vy = my / rho, vz = mz / rho;
+  const double irho = 1.0 / rho;
+  const double vx = mx * irho, vy = my * irho, vz = mz * irho;
   const double kin = 0.5 * (mx * vx + my * vy + mz * vz);
   const double mag = 0.5 * (bx * bx + by * by + bz * bz);
   const double p = (g.gamma - 1.0) * (en - kin - mag);
