@@ -162,10 +162,14 @@ def run(c: OCfg, U, nsteps: int):
     return U, dts[:nsteps]
 
 
-def run_dts(c: OCfg, U, dts) -> np.ndarray:
+def run_dts(c: OCfg, U, dts, allow_unphysical=False) -> np.ndarray:
+    """Steps with the given time steps. With ``allow_unphysical`` the state is
+    returned even where some cell lost positivity (the oracle computes on)."""
     U = _state(c, U).copy()
     d = np.ascontiguousarray(dts, dtype=np.float64)
-    _check(_load().oracle_run_dts(ctypes.byref(c), _ptr(U), len(d), _ptr(d)))
+    rc = _load().oracle_run_dts(ctypes.byref(c), _ptr(U), len(d), _ptr(d))
+    if not (allow_unphysical and rc == -4):
+        _check(rc)
     return U
 
 

@@ -79,9 +79,10 @@ template <class R> __device__ __forceinline__ R min_r(R a, R b) { return (b < a)
 // harmonic van Leer limiter (LIM 1); zero at extrema.
 template <int LIM, class R>
 __device__ __forceinline__ R plm_slope(R dm, R dp) {
-  if (dm * dp <= R(0)) return R(0);
-  if (LIM == 0) return (abs_r(dm) <= abs_r(dp)) ? dm : dp;
-  return div_r(R(2) * dm * dp, dm + dp);
+  const R pr = dm * dp;
+  if (LIM == 0) return (pr <= R(0)) ? R(0) : ((abs_r(dm) <= abs_r(dp)) ? dm : dp);
+  const R q = div_r(R(2) * dm * dp, dm + dp);  // unused (maybe not finite) at extrema
+  return (pr <= R(0)) ? R(0) : q;
 }
 
 // Face-frame primitive state: (rho, u_n, v_t1, v_t2, B_t1, B_t2, p).

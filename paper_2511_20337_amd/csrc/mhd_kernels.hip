@@ -22,17 +22,18 @@ namespace mhd {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Tiled stage kernels. A workgroup of 256 threads owns a tile of cells
-// (16 x 4 x 4 in 3D, 16 x 16 in 2D), one cell per thread.
+// Tiled face kernel. A workgroup owns a tile of cells (16 x 4 x 4 in 3D,
+// 16 x 16 in 2D), one cell per thread.
 template <int DIM>
 struct Tile {
   static constexpr int TX = 16, TY = (DIM == 3) ? 4 : 16, TZ = (DIM == 3) ? 4 : 1;
-  static constexpr int NCORE = TX * TY * TZ;
+  static constexpr int NCORE = TX * TY * TZ;  // also the workgroup size
   // cross-shaped halo: two cells below and one above the tile along each axis
   static constexpr int HX = 3 * TY * TZ, HY = 3 * TX * TZ, HZ = (DIM == 3) ? 3 * TX * TY : 0;
   static constexpr int NPRIM = NCORE + HX + HY + HZ;
 };
-static_assert(Tile<3>::NCORE == kBlock && Tile<2>::NCORE == kBlock, "one cell per thread");
+static_assert(Tile<3>::NCORE % 64 == 0 && Tile<2>::NCORE % 64 == 0 &&
+              Tile<3>::NCORE <= 1024 && Tile<2>::NCORE <= 1024, "whole wavefronts");
 
 // Row tiles for the kernels without LDS staging: a wavefront covers 64
 // consecutive cells of one row (512 contiguous bytes per field).
@@ -225,7 +226,7 @@ __device__ __forceinline__ void pslot_pos(int e, int& x, int& y, int& z) {
 
 // One lower face of direction D of the tile cell (x,y,z) from LDS primitives.
 template <int DIM, int D, int LIM, int RS, class R>
-__device__ __forceinline__ void tile_face(const double (*sp)[Tile<DIM>::NPRIM],
+__device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM],
                                           const double* __restrict__ U, double* __restrict__ FW,
                                           const Geom& g, int x, int y, int z, int64_t c) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
@@ -239,8 +240,8 @@ __device__ __forceinline__ void tile_face(const double (*sp)[Tile<DIM>::NPRIM],
   R wl[7], wr[7];
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
-    const double* P = sp[slot[q]];
-    const R a = (R)P[e[0]], b = (R)P[e[1]], cc = (R)P[e[2]], d = (R)P[e[3]];
+    const R* P = sp[slot[q]];
+    const R a = P[e[0]], b = P[e[1]], cc = P[e[2]], d = P[e[3]];
     wl[q] = b + R(0.5) * plm_slope<LIM, R>(b - a, cc - b);
     wr[q] = cc - R(0.5) * plm_slope<LIM, R>(cc - b, d - cc);
   }
@@ -262,24 +263,25 @@ __device__ __forceinline__ void tile_face(const double (*sp)[Tile<DIM>::NPRIM],
 }
 
 // Face kernel: primitives of the tile and its cross halo are recovered once
-// into LDS, then each thread solves the lower x/y(/z) faces of its cell.
+// (in FP64) into LDS, held in the reconstruction precision R, then each
+// thread solves the lower x/y(/z) faces of its cell.
 template <int DIM, int LIM, int RS, class R>
-__global__ __launch_bounds__(kBlock) void k_faces_tiled(const double* __restrict__ U,
+__global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* __restrict__ U,
                                                         double* __restrict__ FW, Geom g,
                                                         TileGrid tg, int* __restrict__ flag) {
   using T = Tile<DIM>;
-  __shared__ double sp[8][T::NPRIM];
+  __shared__ R sp[8][T::NPRIM];
   int i0, j0, k0;
   tile_origin<DIM>(tg, blockIdx.x, i0, j0, k0);
   bool bad = false;
-  for (int e = threadIdx.x; e < T::NPRIM; e += kBlock) {
+  for (int e = threadIdx.x; e < T::NPRIM; e += T::NCORE) {
     int x, y, z;
     pslot_pos<DIM>(e, x, y, z);
     double V[8];
     bad |= !prim_at<DIM>(U, g, wrap_any(i0 + x, g.nx), wrap_any(j0 + y, g.ny),
                          wrap_any(k0 + z, g.nz), V);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sp[q][e] = V[q];
+    for (int q = 0; q < 8; ++q) sp[q][e] = (R)V[q];
   }
   if (bad) atomicOr(flag, 1);
   __syncthreads();
@@ -370,7 +372,8 @@ hipError_t stage_impl(const StageArgs& a) {
   const TileGrid rg = tile_grid<RowTile>(a.g);
   const unsigned nb = rg.ntiles;
   MHD_TIMED(a, K_FACES,
-            hipLaunchKernelGGL((k_faces_tiled<DIM, LIM, RS, R>), dim3(tg.ntiles), dim3(kBlock), 0,
+            hipLaunchKernelGGL((k_faces_tiled<DIM, LIM, RS, R>), dim3(tg.ntiles),
+                               dim3(Tile<DIM>::NCORE), 0,
                                a.stream, a.U, a.FW, a.g, tg, a.flag));
   MHD_TIMED(a, K_EMF,
             hipLaunchKernelGGL((k_emf<DIM, LIM, R>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,

@@ -68,12 +68,16 @@ def assemble(setup, rho, vx, vy, vz, p, bx, by, bz):
     """Stored state from cell-centre primitives and the staggered field."""
     shape = (setup["nz"], setup["ny"], setup["nx"])
     g = setup["gamma"]
-    f = [np.broadcast_to(np.asarray(a, dtype=np.float64), shape) for a in
-         (rho, vx, vy, vz, p, bx, by, bz)]
-    rho, vx, vy, vz, p, bx, by, bz = f
-    bcx = 0.5 * (bx + np.roll(bx, -1, axis=2))
-    bcy = 0.5 * (by + np.roll(by, -1, axis=1))
-    bcz = 0.5 * (bz + np.roll(bz, -1, axis=0)) if setup["dim"] == 3 else bz
+    rho, vx, vy, vz, p, bx, by, bz = [np.asarray(a, dtype=np.float64) for a in
+                                      (rho, vx, vy, vz, p, bx, by, bz)]
+
+    def face_mean(b, axis):
+        # a constant field is its own face average (and rolling a broadcast
+        # view of a scalar is needlessly slow on large grids)
+        return b if b.ndim == 0 else 0.5 * (b + np.roll(b, -1, axis=axis))
+    bcx = face_mean(bx, 2)
+    bcy = face_mean(by, 1)
+    bcz = face_mean(bz, 0) if setup["dim"] == 3 else bz
     U = np.empty((8,) + shape)
     U[0] = rho
     U[1] = rho * vx

@@ -282,3 +282,69 @@ def test_rhs_parity_mixed(dev, dim, solver):
     assert (err <= 2e-5).all(), err
     ref64 = O.rhs(O.cfg_from(s, precision="fp64"), U)
     assert (rel_err(got, ref64) <= 2e-5).all()
+
+
+def _gpu_divb_rel(U, s):
+    """max |div b| * min(dx) / max |b| of a device state (test-side check)."""
+    dx, dy, dz = W.spacing(s)
+    bx, by, bz = U[5], U[6], U[7]
+    div = (torch.roll(bx, -1, 2) - bx) / dx + (torch.roll(by, -1, 1) - by) / dy + \
+        (torch.roll(bz, -1, 0) - bz) / dz
+    return float(div.abs().max()) * min(dx, dy, dz) / float(U[5:].abs().max())
+
+
+@pytest.mark.parametrize("case", ["blast_640", "lowbeta_384"])
+def test_full_size_mixed_sampled_parity_and_invariants(dev, case):
+    """The large mixed-precision workloads at their full size: the magnetised
+    blast at 640^3 (minmod) and the low-beta Mach-3 turbulence at 384^3. The
+    time step against the oracle on the whole grid; two steps against the
+    oracle's mixed variant (stated FP32 bound) and its FP64 scheme at sampled
+    cells; then eight more steps checked for positivity, conservation and
+    div b on the whole grid (reductions on the device)."""
+    if case == "blast_640":
+        s, U0 = W.blast_3d(640)
+        n = 640
+        # the blast front (r = 0.1, 64 cells from the centre) and random cells
+        cen = [(320, 320, 384), (320, 384, 320), (256, 320, 320), (365, 365, 320),
+               (320, 275, 275), (0, 0, 0), (639, 639, 639)]
+    else:
+        s, U0 = W.turbulence_3d_lowbeta(384)
+        n = 384
+        cen = [(0, 0, 0), (383, 383, 383), (0, 383, 191)]
+    rng = np.random.default_rng(21)
+    cen += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(6)]
+    assert s["precision"] == "mixed"
+    print("%s: dt + 2 steps" % case, flush=True)
+    ctx = ctx_for(s, dev)
+    U = torch.from_numpy(U0).to(dev)
+    dt0 = ctx.dt(U)
+    assert dt0 == pytest.approx(O.dt(O.cfg_from(s), U0), rel=1e-14)
+    ctx.step(U, dt0)
+    dt1 = ctx.dt(U)
+    ctx.step(U, dt1)
+    idx = torch.tensor(cen, device=dev)
+    got = U[:, idx[:, 0], idx[:, 1], idx[:, 2]].T.cpu().numpy()
+    ref_mx = oracle_at_samples(s, U0, [dt0, dt1], cen)
+    s64 = dict(s, precision="fp64")
+    ref_64 = oracle_at_samples(s64, U0, [dt0, dt1], cen)
+    scale = np.abs(U0).max(axis=(1, 2, 3))
+    mom = np.abs(ref_64[:, 1:4]).max()
+    assert mom > 0, "no sample saw motion"
+    # fields at rest or absent (momentum, the blast's b_z) take their group's scale
+    scale[1:4] = np.maximum(scale[1:4], mom)
+    scale[5:8] = np.maximum(scale[5:8], scale[5:8].max())
+    e_mx = (np.abs(got - ref_mx) / scale).max(axis=0)
+    e_64 = (np.abs(got - ref_64) / scale).max(axis=0)
+    print("%s mixed vs oracle-mixed" % case, e_mx, "\nvs fp64", e_64, flush=True)
+    assert (e_mx <= 2e-5).all(), e_mx
+    assert (e_64 <= 1e-4).all(), e_64
+    print("%s invariants: 8 more steps" % case, flush=True)
+    sums0 = U.sum(dim=(1, 2, 3)).cpu().numpy()
+    abs0 = U.abs().sum(dim=(1, 2, 3)).cpu().numpy()
+    ctx.run(U, 8)
+    ctx.check()
+    sums1 = U.sum(dim=(1, 2, 3)).cpu().numpy()
+    # momentum starts at rest in the blast: scale by the sum of |q| after the run too
+    absq = np.maximum(abs0, U.abs().sum(dim=(1, 2, 3)).cpu().numpy())
+    assert (np.abs(sums1 - sums0) <= 1e-12 * absq).all(), (sums1 - sums0) / absq
+    assert _gpu_divb_rel(U, s) <= 1e-12
