@@ -28,29 +28,52 @@ __device__ __forceinline__ int64_t shifted(const Geom& g, int i, int j, int k, i
   return lin(g, i, j, wrap(k + s, g.nz));
 }
 
-// Primitive recovery at cell (i,j,k) (always FP64):
-// V = (rho, vx, vy, vz, p, Bx, By, Bz), B cell-centred as the mean of the two
-// faces (2D: field 7 is already cell-centred). Returns false for an
-// unphysical cell.
+// The stored values primitive recovery at a cell reads: its 8 fields and
+// the staggered field on its three upper faces.
+struct RawCell {
+  double u[8];
+  double bxp, byp, bzp;
+};
+
 template <int DIM>
-__device__ __forceinline__ bool prim_at(const double* __restrict__ U, const Geom& g, int i, int j,
-                                        int k, double* V) {
+__device__ __forceinline__ RawCell load_raw(const double* __restrict__ U, const Geom& g, int i,
+                                            int j, int k) {
   const int64_t n = g.n;
   const int64_t c = lin(g, i, j, k);
-  const double rho = U[c];
-  const double mx = U[n + c], my = U[2 * n + c], mz = U[3 * n + c], en = U[4 * n + c];
-  const double bx = 0.5 * (U[5 * n + c] + U[5 * n + lin(g, wrap(i + 1, g.nx), j, k)]);
-  const double by = 0.5 * (U[6 * n + c] + U[6 * n + lin(g, i, wrap(j + 1, g.ny), k)]);
-  const double bz = (DIM == 3) ? 0.5 * (U[7 * n + c] + U[7 * n + lin(g, i, j, wrap(k + 1, g.nz))])
-                               : U[7 * n + c];
+  RawCell r;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) r.u[q] = U[q * n + c];
+  r.bxp = U[5 * n + lin(g, wrap(i + 1, g.nx), j, k)];
+  r.byp = U[6 * n + lin(g, i, wrap(j + 1, g.ny), k)];
+  r.bzp = (DIM == 3) ? U[7 * n + lin(g, i, j, wrap(k + 1, g.nz))] : 0.0;
+  return r;
+}
+
+// Primitive recovery (always FP64): V = (rho, vx, vy, vz, p, Bx, By, Bz), B
+// cell-centred as the mean of the two faces (2D: field 7 is already
+// cell-centred). Returns false for an unphysical cell.
+template <int DIM>
+__device__ __forceinline__ bool prim_from_raw(const RawCell& r, double gamma, double* V) {
+  const double rho = r.u[0];
+  const double mx = r.u[1], my = r.u[2], mz = r.u[3], en = r.u[4];
+  const double bx = 0.5 * (r.u[5] + r.bxp);
+  const double by = 0.5 * (r.u[6] + r.byp);
+  const double bz = (DIM == 3) ? 0.5 * (r.u[7] + r.bzp) : r.u[7];
   const double irho = 1.0 / rho;
   const double vx = mx * irho, vy = my * irho, vz = mz * irho;
   const double kin = 0.5 * (mx * vx + my * vy + mz * vz);
   const double mag = 0.5 * (bx * bx + by * by + bz * bz);
-  const double p = (g.gamma - 1.0) * (en - kin - mag);
+  const double p = (gamma - 1.0) * (en - kin - mag);
   V[0] = rho; V[1] = vx; V[2] = vy; V[3] = vz; V[4] = p; V[5] = bx; V[6] = by; V[7] = bz;
   return (rho > 0.0) && (p > 0.0) && __builtin_isfinite(p) && __builtin_isfinite(vx) &&
          __builtin_isfinite(vy) && __builtin_isfinite(vz);
+}
+
+// Primitive recovery at cell (i,j,k).
+template <int DIM>
+__device__ __forceinline__ bool prim_at(const double* __restrict__ U, const Geom& g, int i, int j,
+                                        int k, double* V) {
+  return prim_from_raw<DIM>(load_raw<DIM>(U, g, i, j, k), g.gamma, V);
 }
 
 // Reconstructed face-frame states of the lower D-face of cell (i,j,k):

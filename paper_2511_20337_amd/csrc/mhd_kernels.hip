@@ -1,7 +1,7 @@
 // HIP kernels of the ideal-MHD step for gfx950, and their launchers.
 //
 // One stage of the SSP-RK2 step is three launches:
-//   k_faces_march — 3D: 16 x 16 columns of cells marching along z, with the
+//   k_faces_march — 3D: 64 x 4 columns of cells marching along z, with the
 //                   primitives of three planes and a cross halo in LDS; per
 //                   cell its lower x/y/z faces: PLM, HLL/HLLD; writes the
 //                   face fluxes and the alpha+-, HLL-weighted velocities the
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
 }
 
 // ---------------------------------------------------------------------------
-// 3D face kernel marching along z. A workgroup owns a 16 x 16 column of cells
+// 3D face kernel marching along z. A workgroup owns a 64 x 4 column of cells
 // and walks a run of planes k0 <= k < k1, one cell of each plane per thread.
 // LDS holds the primitives of planes k-1, k, k+1 of the column (a ring of
 // three), the x/y cross halo (two cells below, one above) of plane k, and
@@ -305,10 +305,13 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
 // z-face of cell k takes its left state V_{k-1} + slope_{k-1}/2 from the
 // previous plane's step, where the thread computed slope_{k-1} for the right
 // state of the face below; each z slope is thus evaluated once. Per plane only
-// the core of plane k+2 and the halo of plane k+1 are recovered, so each cell's
-// state is read about 1.4 times, against 2.7 times with cubic tiles.
+// the core of plane k+2 and the halo of plane k+1 are recovered; the raw state
+// of the own cell of plane k+2 is loaded before the faces of plane k are
+// solved, so its latency hides behind them. (Measured at 256^3: 64 x 4
+// columns beat 16 x 16 ones, and dealing x-neighbour columns to one XCD is
+// slower than the natural order.)
 struct March {
-  static constexpr int TX = 16, TY = 16, NCORE = TX * TY;
+  static constexpr int TX = 64, TY = 4, NCORE = TX * TY;
   static constexpr int NHALO = 3 * TY + 3 * TX;  // x-halo then y-halo
   static constexpr int NQ = 7;                   // ring quantities: V slots 0..6
 };
@@ -390,11 +393,9 @@ __device__ __forceinline__ void march_xy(int rp, int bp, int xx, int yy, int& o,
 
 // Writes the nine records of a lower face from its reconstructed states.
 template <int D, int RS, class R>
-__device__ __forceinline__ void march_solve(const R* wl, const R* wr,
-                                            const double* __restrict__ U,
+__device__ __forceinline__ void march_solve(const R* wl, const R* wr, R bn,
                                             double* __restrict__ FW, const Geom& g, int64_t c) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const R bn = (R)U[(F_BX + D) * g.n + c];
   RiemannOut<R> o;
   riemann<RS, R>((R)g.gamma, wl, wr, bn, o);
   const int64_t n = g.n;
@@ -414,7 +415,7 @@ __device__ __forceinline__ void march_solve(const R* wl, const R* wr,
 // stencil cells (offsets o*, strides s*, B_z offsets b*), then the solver.
 template <int D, int LIM, int RS, class R>
 __device__ __forceinline__ void march_face_xy(const R* lds, const int* o, const int* st,
-                                              const int* ob, const double* __restrict__ U,
+                                              const int* ob, R bn,
                                               double* __restrict__ FW, const Geom& g, int64_t c) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   constexpr int slot[7] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4};
@@ -428,7 +429,7 @@ __device__ __forceinline__ void march_face_xy(const R* lds, const int* o, const 
     wl[q] = v[1] + R(0.5) * plm_slope<LIM, R>(v[1] - v[0], v[2] - v[1]);
     wr[q] = v[2] - R(0.5) * plm_slope<LIM, R>(v[2] - v[1], v[3] - v[2]);
   }
-  march_solve<D, RS, R>(wl, wr, U, FW, g, c);
+  march_solve<D, RS, R>(wl, wr, bn, FW, g, c);
 }
 
 template <int LIM, int RS, class R>
@@ -484,18 +485,29 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
   for (int k = k0; k < k1; ++k) {
     const int rm = (k - 1 - kbase) % 3, r0 = (k - kbase) % 3, rp = (k + 1 - kbase) % 3;
     const int b0 = (k - kbase) & 1;
+    const bool more = k + 1 < k1;
+    // normal fields of this cell's faces, then the raw state of the own cell
+    // of plane k+2, in flight while the faces are solved
+    const int64_t c = lin(g, i, j, k);
+    double bnx = 0.0, bny = 0.0, bnz = 0.0;
     if (inside) {
-      const int64_t c = lin(g, i, j, k);
+      bnx = U[5 * g.n + c];
+      bny = U[6 * g.n + c];
+      bnz = U[7 * g.n + c];
+    }
+    RawCell nxt;
+    if (more) nxt = load_raw<3>(U, g, wrap_any(i, g.nx), wrap_any(j, g.ny), wrap_any(k + 2, g.nz));
+    if (inside) {
       int o[4], st[4], ob[4];
       march_xy(r0, b0, x - 2, y, o[0], st[0], ob[0]);
       march_xy(r0, b0, x - 1, y, o[1], st[1], ob[1]);
       march_xy(r0, b0, x, y, o[2], st[2], ob[2]);
       march_xy(r0, b0, x + 1, y, o[3], st[3], ob[3]);
-      march_face_xy<0, LIM, RS, R>(lds, o, st, ob, U, FW, g, c);
+      march_face_xy<0, LIM, RS, R>(lds, o, st, ob, (R)bnx, FW, g, c);
       march_xy(r0, b0, x, y - 2, o[0], st[0], ob[0]);
       march_xy(r0, b0, x, y - 1, o[1], st[1], ob[1]);
       march_xy(r0, b0, x, y + 1, o[3], st[3], ob[3]);
-      march_face_xy<1, LIM, RS, R>(lds, o, st, ob, U, FW, g, c);
+      march_face_xy<1, LIM, RS, R>(lds, o, st, ob, (R)bny, FW, g, c);
       // z face: left state carried from the plane below; the slope of cell k
       // gives the right state and the next plane's left state
       R wl[7], wr[7];
@@ -510,12 +522,15 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
         wr[q] = bb - R(0.5) * dlt;
         zl[q] = bb + R(0.5) * dlt;
       }
-      march_solve<2, RS, R>(wl, wr, U, FW, g, c);
+      march_solve<2, RS, R>(wl, wr, (R)bnz, FW, g, c);
     }
-    if (k + 1 < k1) {
+    if (more) {
       __syncthreads();  // plane k-1, B_z of plane k and the halo of plane k are free
+      double W[8];
+      bad |= !prim_from_raw<3>(nxt, g.gamma, W);
       R V[8];
-      bad |= !march_prim<R>(U, g, i, j, k + 2, V);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) V[q] = (R)W[q];
       march_put_core<R>(lds, rm, b0, cidx, V);  // plane k+2: ring (k+2-kbase)%3 == rm
       if (haloer) {
         R H[8];

@@ -121,8 +121,10 @@ def _run_gpu(ctx, U0, nsteps, dev):
 
 
 @pytest.mark.parametrize("case", ["orszag_tang_128", "turbulence_64", "blast_32",
-                                  "kh_64", "ragged2", "ragged3"])
+                                  "kh_64", "ragged2", "ragged3", "ragged3_runs"])
 def test_ten_step_parity_fp64(dev, case):
+    """Ten CFL steps against the oracle. ragged3_runs (20 x 18 x 37) has
+    partial 16 x 16 columns in x and y and z-runs of 16, 16 and 5 planes."""
     if case == "orszag_tang_128":
         s, U0 = W.orszag_tang_2d(128)
     elif case == "turbulence_64":
@@ -133,8 +135,10 @@ def test_ten_step_parity_fp64(dev, case):
         s, U0, _ = W.kelvin_helmholtz_2d(64)
     elif case == "ragged2":
         s, U0 = ragged(2, "minmod", "hlld")
-    else:
+    elif case == "ragged3":
         s, U0 = ragged(3, "vanleer", "hll")
+    else:
+        s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
     print("10-step parity", case, flush=True)
     ctx = ctx_for(s, dev)
     got, dts = _run_gpu(ctx, U0, 10, dev)
