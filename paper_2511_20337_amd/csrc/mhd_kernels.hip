@@ -41,6 +41,11 @@ struct RowTile {
   static constexpr int TX = 64, TY = 4, TZ = 1;
 };
 
+struct MarchGrid {
+  int ntx, nty, nzc, lz;  // column tiles in x, y; runs of lz planes along z
+  unsigned nblocks;
+};
+
 struct TileGrid {
   int ntx, nty, ntz;
   unsigned ntiles;
@@ -82,6 +87,25 @@ __device__ __forceinline__ bool row_cell(const Geom& g, const TileGrid& tg, int&
   return i < g.nx && j < g.ny && k < g.nz;
 }
 
+// Upwind edge EMF from its inputs: alpha+- of the two a-faces touching the
+// edge (below the edge along B, then the cell's own), of the two b-faces
+// (below along A, then own); the face velocity v_A and the field b_B on the
+// b-faces at A-offsets -2..+1, and v_B and b_A on the a-faces at B-offsets
+// -2..+1, each reconstructed toward the edge.
+template <int LIM, class R>
+__device__ __forceinline__ double emf_core(R apa_m, R apa_c, R ama_m, R ama_c, R apb_m, R apb_c,
+                                           R amb_m, R amb_c, const R* vbA, const R* bB,
+                                           const R* vaB, const R* bA) {
+  const R apa = max_r(apa_m, apa_c), ama = max_r(ama_m, ama_c);
+  const R apb = max_r(apb_m, apb_c), amb = max_r(amb_m, amb_c);
+  R vW, vE, bW, bE, vS, vN, bS, bN;
+  edge_pair<LIM, R>(vbA[0], vbA[1], vbA[2], vbA[3], vW, vE);
+  edge_pair<LIM, R>(bB[0], bB[1], bB[2], bB[3], bW, bE);
+  edge_pair<LIM, R>(vaB[0], vaB[1], vaB[2], vaB[3], vS, vN);
+  edge_pair<LIM, R>(bA[0], bA[1], bA[2], bA[3], bS, bN);
+  return (double)uct<R>(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN);
+}
+
 // Edge EMF of component C at cell (i,j,k): the edge at the lower A- and
 // lower B-position of the cell, (A, B) = (C+1, C+2) cyclic.
 template <int C, int LIM, class R>
@@ -94,25 +118,126 @@ __device__ __forceinline__ double emf_comp(const double* __restrict__ U,
   const double* fb = FW + (int64_t)B * NSLOT * n;  // b-faces (normal B)
   const int64_t cmb = shifted<B>(g, i, j, k, -1);  // a-face below the edge along B
   const int64_t cma = shifted<A>(g, i, j, k, -1);  // b-face below the edge along A
-  const R apa = max_r((R)fa[S_AP * n + cmb], (R)fa[S_AP * n + c]);
-  const R ama = max_r((R)fa[S_AM * n + cmb], (R)fa[S_AM * n + c]);
-  const R apb = max_r((R)fb[S_AP * n + cma], (R)fb[S_AP * n + c]);
-  const R amb = max_r((R)fb[S_AM * n + cma], (R)fb[S_AM * n + c]);
-  // W/E: on b-faces, v_A (slot V2 of the B frame) and b_B, along A
   const int64_t a2 = shifted<A>(g, i, j, k, -2), a1 = shifted<A>(g, i, j, k, 1);
-  const double* vbA = fb + S_V2 * n;
-  const double* bB = U + (F_BX + B) * n;
-  R vW, vE, bW, bE;
-  edge_pair<LIM, R>((R)vbA[a2], (R)vbA[cma], (R)vbA[c], (R)vbA[a1], vW, vE);
-  edge_pair<LIM, R>((R)bB[a2], (R)bB[cma], (R)bB[c], (R)bB[a1], bW, bE);
-  // S/N: on a-faces, v_B (slot V1 of the A frame) and b_A, along B
   const int64_t b2 = shifted<B>(g, i, j, k, -2), b1 = shifted<B>(g, i, j, k, 1);
-  const double* vaB = fa + S_V1 * n;
-  const double* bA = U + (F_BX + A) * n;
-  R vS, vN, bS, bN;
-  edge_pair<LIM, R>((R)vaB[b2], (R)vaB[cmb], (R)vaB[c], (R)vaB[b1], vS, vN);
-  edge_pair<LIM, R>((R)bA[b2], (R)bA[cmb], (R)bA[c], (R)bA[b1], bS, bN);
-  return (double)uct<R>(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN);
+  const double* vbA = fb + S_V2 * n;  // on b-faces, v_A (slot V2 of the B frame)
+  const double* bBf = U + (F_BX + B) * n;
+  const double* vaB = fa + S_V1 * n;  // on a-faces, v_B (slot V1 of the A frame)
+  const double* bAf = U + (F_BX + A) * n;
+  const R wv[4] = {(R)vbA[a2], (R)vbA[cma], (R)vbA[c], (R)vbA[a1]};
+  const R wb[4] = {(R)bBf[a2], (R)bBf[cma], (R)bBf[c], (R)bBf[a1]};
+  const R sv[4] = {(R)vaB[b2], (R)vaB[cmb], (R)vaB[c], (R)vaB[b1]};
+  const R sb[4] = {(R)bAf[b2], (R)bAf[cmb], (R)bAf[c], (R)bAf[b1]};
+  return emf_core<LIM, R>((R)fa[S_AP * n + cmb], (R)fa[S_AP * n + c], (R)fa[S_AM * n + cmb],
+                          (R)fa[S_AM * n + c], (R)fb[S_AP * n + cma], (R)fb[S_AP * n + c],
+                          (R)fb[S_AM * n + cma], (R)fb[S_AM * n + c], wv, wb, sv, sb);
+}
+
+// 3D EMF kernel marching along z over 64 x 4 columns: the inputs of E_x and
+// E_y that are offset along z (alpha+- of the y- and x-faces one plane down,
+// v and b on those faces two planes down to one up) ride in registers from
+// plane to plane, so each is loaded once per run instead of up to four times.
+struct EmfCol {
+  static constexpr int TX = 64, TY = 4;
+};
+
+template <int LIM, class R>
+__global__ __launch_bounds__(kBlock) void k_emf_march(const double* __restrict__ U,
+                                                      const double* __restrict__ FW,
+                                                      double* __restrict__ EW, Geom g,
+                                                      MarchGrid mg) {
+  const unsigned b = blockIdx.x;
+  const int tx = (int)(b % (unsigned)mg.ntx);
+  const unsigned r = b / (unsigned)mg.ntx;
+  const int ty = (int)(r % (unsigned)mg.nty);
+  const int zc = (int)(r / (unsigned)mg.nty);
+  const int i = tx * EmfCol::TX + (int)threadIdx.x % EmfCol::TX;
+  const int j = ty * EmfCol::TY + (int)threadIdx.x / EmfCol::TX;
+  if (i >= g.nx || j >= g.ny) return;
+  const int k0 = zc * mg.lz;
+  const int k1 = min(k0 + mg.lz, g.nz);
+  const int64_t n = g.n;
+  const double* fx = FW;
+  const double* fy = FW + (int64_t)NSLOT * n;
+  const double* fz = FW + (int64_t)2 * NSLOT * n;
+  const double* bx = U + F_BX * n;
+  const double* by = U + F_BY * n;
+  const double* bz = U + F_BZ * n;
+  // planes k-2 .. k+1 of this column: v_z on y-faces and b_y (E_x), v_z on
+  // x-faces and b_x (E_y); alpha+- of y- and x-faces on planes k-1, k
+  R yv[4], yb[4], xv[4], xb[4], yap[2], yam[2], xap[2], xam[2];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int64_t cs = lin(g, i, j, wrap_any(k0 - 2 + s, g.nz));
+    yv[s] = (R)fy[S_V1 * n + cs];
+    yb[s] = (R)by[cs];
+    xv[s] = (R)fx[S_V2 * n + cs];
+    xb[s] = (R)bx[cs];
+  }
+  {
+    const int64_t cm = lin(g, i, j, wrap_any(k0 - 1, g.nz));
+    yap[0] = (R)fy[S_AP * n + cm];
+    yam[0] = (R)fy[S_AM * n + cm];
+    xap[0] = (R)fx[S_AP * n + cm];
+    xam[0] = (R)fx[S_AM * n + cm];
+  }
+  const int im2 = wrap(i - 2, g.nx), im1 = wrap(i - 1, g.nx), ip1 = wrap(i + 1, g.nx);
+  const int jm2 = wrap(j - 2, g.ny), jm1 = wrap(j - 1, g.ny), jp1 = wrap(j + 1, g.ny);
+  for (int k = k0; k < k1; ++k) {
+    const int64_t c = lin(g, i, j, k);
+    const int64_t cp = lin(g, i, j, wrap(k + 1, g.nz));
+    const int64_t cjm2 = lin(g, i, jm2, k), cjm1 = lin(g, i, jm1, k), cjp1 = lin(g, i, jp1, k);
+    const int64_t cim2 = lin(g, im2, j, k), cim1 = lin(g, im1, j, k), cip1 = lin(g, ip1, j, k);
+    // all FP64 loads of this plane first, then the conversions to R (keeps
+    // the loads in flight together when R is float)
+    const double* vz2 = fz + S_V2 * n;
+    const double* vz1 = fz + S_V1 * n;
+    double d[24];
+    d[0] = fy[S_V1 * n + cp]; d[1] = by[cp]; d[2] = fx[S_V2 * n + cp]; d[3] = bx[cp];
+    d[4] = fy[S_AP * n + c]; d[5] = fy[S_AM * n + c]; d[6] = fx[S_AP * n + c];
+    d[7] = fx[S_AM * n + c];
+    d[8] = vz2[cjm2]; d[9] = vz2[cjm1]; d[10] = vz2[c]; d[11] = vz2[cjp1];
+    d[12] = bz[cjm2]; d[13] = bz[cjm1]; d[14] = bz[c]; d[15] = bz[cjp1];
+    d[16] = vz1[cim2]; d[17] = vz1[cim1]; d[18] = vz1[c]; d[19] = vz1[cip1];
+    d[20] = bz[cim2]; d[21] = bz[cim1]; d[22] = bz[cip1];
+    d[23] = fz[S_AP * n + cjm1];
+    const double zapc = fz[S_AP * n + c], zamj = fz[S_AM * n + cjm1], zamc = fz[S_AM * n + c];
+    const double zapi = fz[S_AP * n + cim1], zami = fz[S_AM * n + cim1];
+    yv[3] = (R)d[0];
+    yb[3] = (R)d[1];
+    xv[3] = (R)d[2];
+    xb[3] = (R)d[3];
+    yap[1] = (R)d[4];
+    yam[1] = (R)d[5];
+    xap[1] = (R)d[6];
+    xam[1] = (R)d[7];
+    // E_x: (A, B) = (y, z); a-faces are y-faces, b-faces z-faces
+    {
+      const R wv[4] = {(R)d[8], (R)d[9], (R)d[10], (R)d[11]};
+      const R wb[4] = {(R)d[12], (R)d[13], (R)d[14], (R)d[15]};
+      EW[c] = emf_core<LIM, R>(yap[0], yap[1], yam[0], yam[1], (R)d[23], (R)zapc, (R)zamj,
+                               (R)zamc, wv, wb, yv, yb);
+    }
+    // E_y: (A, B) = (z, x); a-faces are z-faces, b-faces x-faces
+    {
+      const R sv[4] = {(R)d[16], (R)d[17], (R)d[18], (R)d[19]};
+      const R sb[4] = {(R)d[20], (R)d[21], (R)d[14], (R)d[22]};
+      EW[n + c] = emf_core<LIM, R>((R)zapi, (R)zapc, (R)zami, (R)zamc, xap[0], xap[1], xam[0],
+                                   xam[1], xv, xb, sv, sb);
+    }
+    EW[2 * n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      yv[s] = yv[s + 1];
+      yb[s] = yb[s + 1];
+      xv[s] = xv[s + 1];
+      xb[s] = xb[s + 1];
+    }
+    yap[0] = yap[1];
+    yam[0] = yam[1];
+    xap[0] = xap[1];
+    xam[0] = xam[1];
+  }
 }
 
 template <int DIM, int LIM, class R>
@@ -317,10 +442,7 @@ struct March {
 };
 static_assert(March::NCORE == kBlock, "one column cell per thread");
 
-struct MarchGrid {
-  int ntx, nty, nzc, lz;  // column tiles in x, y; runs of lz planes along z
-  unsigned nblocks;
-};
+
 // Planes per run: the prologue costs two extra planes per run, shorter runs
 // give more workgroups (4096 at 256^3 with 16; 16 measured faster than 32).
 constexpr int kMarchRun = 16;
@@ -635,9 +757,21 @@ hipError_t stage_impl(const StageArgs& a) {
               hipLaunchKernelGGL((k_faces_tiled<DIM, LIM, RS, R>), dim3(tg.ntiles),
                                  dim3(Tile<DIM>::NCORE), 0, a.stream, a.U, a.FW, a.g, tg, a.flag));
   }
-  MHD_TIMED(a, K_EMF,
-            hipLaunchKernelGGL((k_emf<DIM, LIM, R>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,
-                               a.FW, a.EW, a.g, rg));
+  if constexpr (DIM == 3) {
+    MarchGrid eg;
+    eg.ntx = (a.g.nx + EmfCol::TX - 1) / EmfCol::TX;
+    eg.nty = (a.g.ny + EmfCol::TY - 1) / EmfCol::TY;
+    eg.lz = a.g.nz < kMarchRun ? a.g.nz : kMarchRun;
+    eg.nzc = (a.g.nz + eg.lz - 1) / eg.lz;
+    eg.nblocks = (unsigned)eg.ntx * (unsigned)eg.nty * (unsigned)eg.nzc;
+    MHD_TIMED(a, K_EMF,
+              hipLaunchKernelGGL((k_emf_march<LIM, R>), dim3(eg.nblocks), dim3(kBlock), 0,
+                                 a.stream, a.U, a.FW, a.EW, a.g, eg));
+  } else {
+    MHD_TIMED(a, K_EMF,
+              hipLaunchKernelGGL((k_emf<DIM, LIM, R>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,
+                                 a.FW, a.EW, a.g, rg));
+  }
   switch (a.stage) {
     case 3:  // face and edge records only (the adjoint's forward recompute)
       break;
