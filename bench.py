@@ -49,7 +49,7 @@ KERNEL_BOUND = {"faces": "alu", "emf": "hbm", "update": "hbm", "cfl": "hbm"}
 # HBM bytes per cell of one launch measured with rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.0 and 1.0), for the
 # kernels as they stand; see profiles/.
-KERNEL_TRAFFIC = {}
+KERNEL_TRAFFIC = {"faces": 202.3 + 216.0}
 
 
 def time_gpu(setup, U0, steps, warmup, timing=True):
@@ -106,22 +106,44 @@ def time_adjoint(n, nsteps, every):
     return nsteps / (t2 - t1), nsteps / (t1 - t0)
 
 
-def cpu_baseline(n_sample: int, setup_fn):
-    """The oracle, untuned, on the same generator at n_sample^3: one dt + one
-    RK2 step with every host thread this process may use."""
+def time_adjoint_blast(n, nsteps, every):
+    """Magnetised blast n^3 in FP64: N forward steps with checkpoints, then the
+    checkpointed backward. Returns adjoint steps/s and forward steps/s."""
+    import torch
+    from paper_2511_20337_amd import adjoint as AD, mhd, workloads as W
+    dev = torch.device("cuda:0")
+    s, U = W.blast_3d(n, precision="fp64")
+    ctx = mhd.Context(s, dev, with_adjoint=True)
+    U0 = torch.from_numpy(U).to(dev)
+    del U
+    dts, _ = AD.record_dts(ctx, U0, nsteps)
+    x = U0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = AD.run_with_grad(ctx, x, dts, every=every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out.backward(torch.ones_like(out))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return nsteps / (t2 - t1), nsteps / (t1 - t0)
+
+
+def cpu_baseline(n_sample: int, setup_fn, steps: int = 2):
+    """The oracle, untuned, on the same generator at n_sample^3: `steps` steps
+    (CFL dt + RK2 step each) with every host thread this process may use."""
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     setup, U = setup_fn(n_sample)
     c = O.cfg_from(setup, nthreads=threads)
     t0 = time.perf_counter()
-    dt = O.dt(c, U)
-    O.step(c, U, dt)
+    O.run(c, U, steps)
     el = time.perf_counter() - t0
     cells = n_sample ** 3
-    return {"value": cells / el / 1e6, "unit": "Mcell-updates/s", "cores": threads,
+    return {"value": cells * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": "same turbulence generator at %d^3, 1 CFL dt + 1 RK2 step (%.1f s), "
-                      "%d OpenMP threads" % (n_sample, el, threads)}
+            "sample": "same turbulence generator at %d^3, %d steps of CFL dt + RK2 step "
+                      "(%.1f s), %d OpenMP threads" % (n_sample, steps, el, threads)}
 
 
 def copy_probe(mib: int) -> int:
@@ -148,7 +170,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256, help="grid cells per side")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-n", type=int, default=128, help="oracle sample size per side")
+    ap.add_argument("--cpu-n", type=int, default=256, help="oracle sample size per side")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle sample steps")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision and adjoint measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -231,14 +254,34 @@ def main(argv=None):
                         "config": {"workload": "turbulence_3d_lowbeta_%d" % args.n, "mach": 3,
                                    "beta": 0.01, "precision": "mixed"},
                         "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_m.items() if v[1]}}
+        out["large"] = {}
+        for name, fn, n in (("turbulence_3d_lowbeta_384", W.turbulence_3d_lowbeta, 384),
+                            ("blast_3d_640", W.blast_3d, 640)):
+            log("mixed precision, large grid: %s" % name)
+            sl, Ul = fn(n)
+            steps_l = max(1, args.steps // 5)
+            el_l, kt_l, _, phys_l = time_gpu(sl, Ul, steps_l, 1)
+            del Ul
+            vl = n ** 3 * steps_l / el_l / 1e6
+            out["large"][name] = {"value": vl, "unit": "Mcell-updates/s", "steps": steps_l,
+                                  "ms_per_step": el_l / steps_l * 1e3, "physical": phys_l,
+                                  "precision": sl["precision"], "limiter": sl["limiter"],
+                                  "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_l.items()
+                                              if v[1]}}
         log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, checkpoints every 8")
         adj, fwd = time_adjoint(512, 64, 8)
         out["adjoint"] = {"value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
                           "config": {"workload": "kelvin_helmholtz_2d_512", "steps": 64,
                                      "checkpoint_every": 8}}
+        log("adjoint: blast 256^3 FP64, 16 steps, checkpoints every 4")
+        adj3, fwd3 = time_adjoint_blast(256, 16, 4)
+        out["adjoint_3d"] = {"value": adj3, "unit": "adjoint steps/s",
+                             "forward_steps_per_s": fwd3,
+                             "config": {"workload": "blast_3d_256_fp64", "steps": 16,
+                                        "checkpoint_every": 4}}
     if not args.no_cpu:
         log("cpu baseline: oracle at %d^3" % args.cpu_n)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, make)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, make, args.cpu_steps)
     print(json.dumps(out), flush=True)
     return 0
 

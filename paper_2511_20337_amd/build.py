@@ -17,6 +17,9 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no automatic FMA contraction (the sources also say so with a pragma):
+    # forward and adjoint kernels must round the same expressions the same way
+    "-ffp-contract=off",
     "-I", os.path.join(ROOT, "include"),
 ]
 

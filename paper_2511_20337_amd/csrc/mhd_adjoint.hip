@@ -52,14 +52,23 @@ __device__ __forceinline__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
 __device__ __forceinline__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
 __device__ __forceinline__ bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
 __device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
-// found by argument-dependent lookup from the solver template
+// Found by argument-dependent lookup from the solver template. The value
+// parts use the same quotient, reciprocal and square root as the forward
+// kernels, so a dual pass reproduces the forward values bit for bit and
+// takes the same branches.
 __device__ __forceinline__ Dual sqrt_r(Dual x) {
-  const double s = __builtin_sqrt(x.v);
+  const double s = ::mhd::sqrt_r(x.v);
   return Dual(s, s > 0.0 ? 0.5 * x.d / s : 0.0);
 }
 __device__ __forceinline__ Dual abs_r(Dual x) { return x.v < 0.0 ? -x : x; }
-__device__ __forceinline__ Dual rcp_r(Dual x) { return Dual(1.0) / x; }
-__device__ __forceinline__ Dual div_r(Dual a, Dual b) { return a / b; }
+__device__ __forceinline__ Dual rcp_r(Dual x) {
+  const double r = ::mhd::rcp_r(x.v);
+  return Dual(r, -x.d * r * r);
+}
+__device__ __forceinline__ Dual div_r(Dual a, Dual b) {
+  const double q = ::mhd::div_r(a.v, b.v);
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
 
 // Edge-partial slots: d E / d input times Ebar.
 enum : int { E_APA = 0, E_AMA, E_VW, E_BW, E_VE, E_BE, E_APB, E_AMB, E_VS, E_BS, E_VN, E_BN, NE };

@@ -13,6 +13,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Every floating-point operation is evaluated as written: no automatic fusion
+// of a multiply and an add into an FMA (explicit __builtin_fma calls stay).
+// The adjoint re-evaluates reconstruction and the Riemann solver in other
+// kernels and in dual numbers; with contraction left to the compiler, the same
+// source could round differently there than in the forward kernels, and at
+// near-ties (a limiter at a local extremum, min/max of equal wave speeds,
+// the sign of the contact speed) take the other branch. This pragma applies
+// to every function defined after it in the translation unit.
+#pragma clang fp contract(off)
+
 namespace mhd {
 
 enum : int { F_RHO = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_EN = 4, F_BX = 5, F_BY = 6, F_BZ = 7 };
