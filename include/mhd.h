@@ -127,6 +127,13 @@ mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const do
                             double* Ubar_n, double* dtbar, void* ws, size_t ws_bytes,
                             void* stream);
 
+/* As mhd_adjoint_step, with dt-bar written to the device double *dtbar_dev
+ * (NULL: not computed) and no host synchronisation, for loops over many
+ * steps (the checkpointed N-step gradient). */
+mhd_status mhd_adjoint_step_device(mhd_ctx* ctx, const double* U_n, double dt,
+                                   const double* Ubar_np1, double* Ubar_n, double* dtbar_dev,
+                                   void* ws, size_t ws_bytes, void* stream);
+
 /* Synchronise the stream and report (and clear) the unphysical flag. */
 mhd_status mhd_check(mhd_ctx* ctx, void* ws, size_t ws_bytes, void* stream);
 

@@ -44,7 +44,7 @@ class MHDSteps(torch.autograd.Function):
         dts = fctx.dt_list
         n = len(dts)
         bar = gU.detach().contiguous().clone()
-        dtbar = torch.zeros(fctx.dts_shape, dtype=torch.float64)
+        dtbar_dev = torch.zeros(n, dtype=torch.float64, device=bar.device)
         tmp = torch.empty_like(bar)
         for start in reversed(sorted(fctx.checkpoints)):
             stop = min(start + fctx.every, n)
@@ -55,10 +55,10 @@ class MHDSteps(torch.autograd.Function):
                 solver.step(U, dts[s])
                 states.append(U)
             for s in range(stop - 1, start - 1, -1):
-                _, db = solver.adjoint_step(states[s - start], dts[s], bar, want_dtbar=True,
-                                            out=tmp)
-                dtbar[s] = db
+                solver.adjoint_step(states[s - start], dts[s], bar, out=tmp,
+                                    dtbar_out=dtbar_dev[s:s + 1])
                 bar, tmp = tmp, bar
+        dtbar = dtbar_dev.cpu().reshape(fctx.dts_shape)
         return bar, dtbar, None, None
 
 

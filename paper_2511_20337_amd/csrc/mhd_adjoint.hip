@@ -42,7 +42,7 @@ __device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.
 __device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
 __device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
 __device__ __forceinline__ Dual operator*(Dual a, Dual b) {
-  return Dual(a.v * b.v, a.d * b.v + a.v * b.d);
+  return Dual(a.v * b.v, __builtin_fma(a.d, b.v, a.v * b.d));
 }
 __device__ __forceinline__ Dual operator/(Dual a, Dual b) {
   const double q = a.v / b.v;
@@ -56,9 +56,12 @@ __device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; 
 // parts use the same quotient, reciprocal and square root as the forward
 // kernels, so a dual pass reproduces the forward values bit for bit and
 // takes the same branches.
+// (Tangents may round differently from their exact quotients; only the
+// values steer branches.)
 __device__ __forceinline__ Dual sqrt_r(Dual x) {
-  const double s = ::mhd::sqrt_r(x.v);
-  return Dual(s, s > 0.0 ? 0.5 * x.d / s : 0.0);
+  double h;
+  const double s = ::mhd::sqrt_r_half(x.v, h);
+  return Dual(s, s > 0.0 ? x.d * h : 0.0);
 }
 __device__ __forceinline__ Dual abs_r(Dual x) { return x.v < 0.0 ? -x : x; }
 __device__ __forceinline__ Dual rcp_r(Dual x) {
@@ -66,8 +69,9 @@ __device__ __forceinline__ Dual rcp_r(Dual x) {
   return Dual(r, -x.d * r * r);
 }
 __device__ __forceinline__ Dual div_r(Dual a, Dual b) {
-  const double q = ::mhd::div_r(a.v, b.v);
-  return Dual(q, (a.d - q * b.d) / b.v);
+  double r;
+  const double q = ::mhd::div_r_rcp(a.v, b.v, r);
+  return Dual(q, __builtin_fma(-q, b.d, a.d) * r);
 }
 
 // Edge-partial slots: d E / d input times Ebar.

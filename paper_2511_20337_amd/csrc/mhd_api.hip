@@ -307,15 +307,16 @@ mhd_status mhd_rhs(mhd_ctx* ctx, const double* U, double* L, void* ws, size_t ws
   return MHD_OK;
 }
 
-mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const double* Ubar_np1,
-                            double* Ubar_n, double* dtbar, void* ws, size_t ws_bytes,
-                            void* stream) {
+// Shared body of the two adjoint entry points: dt-bar goes to the device
+// double dtbar_dev when want_dtbar (nullptr: the workspace slot).
+static mhd_status adjoint_impl(mhd_ctx* ctx, const double* U_n, double dt, const double* Ubar_np1,
+                               double* Ubar_n, bool want_dtbar, double* dtbar_dev, void* ws,
+                               size_t ws_bytes, hipStream_t s) {
   if (!ctx) return MHD_ERR_INVALID;
   if (!U_n || !Ubar_np1 || !Ubar_n || !(dt > 0.0) || !std::isfinite(dt)) return MHD_ERR_INVALID;
   if (Ubar_n == Ubar_np1 || Ubar_n == U_n) return MHD_ERR_INVALID;
   if (ctx->cfg.precision != MHD_PREC_FP64) return MHD_ERR_UNSUPPORTED;
   if (!ws_ok(ctx, ws, ws_bytes, true)) return MHD_ERR_WORKSPACE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   mhd::AdjointArgs a{};
   a.dim = ctx->cfg.dim;
   a.limiter = ctx->cfg.limiter;
@@ -329,19 +330,34 @@ mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const do
   a.FW = reinterpret_cast<double*>(base(ws) + ctx->off_fw);
   a.EW = reinterpret_cast<double*>(base(ws) + ctx->off_ew);
   a.scratch = reinterpret_cast<double*>(base(ws) + ctx->off_adj);
-  a.dtbar_dev = ws_dt(ws);
-  a.want_dtbar = dtbar != nullptr;
+  a.dtbar_dev = dtbar_dev ? dtbar_dev : ws_dt(ws);
+  a.want_dtbar = want_dtbar;
   a.flag = ws_flag(ws);
   a.stream = s;
   hipError_t e = mhd::launch_adjoint_step(a);
   if (e == hipErrorNotSupported) return MHD_ERR_UNSUPPORTED;
   if (e != hipSuccess) return device_fail(ctx, e, "adjoint");
-  if (dtbar) {
-    e = hipMemcpyAsync(dtbar, ws_dt(ws), sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return device_fail(ctx, e, "dtbar copy");
-  }
   return MHD_OK;
+}
+
+mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const double* Ubar_np1,
+                            double* Ubar_n, double* dtbar, void* ws, size_t ws_bytes,
+                            void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mhd_status st = adjoint_impl(ctx, U_n, dt, Ubar_np1, Ubar_n, dtbar != nullptr, nullptr, ws,
+                               ws_bytes, s);
+  if (st != MHD_OK || !dtbar) return st;
+  hipError_t e = hipMemcpyAsync(dtbar, ws_dt(ws), sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return device_fail(ctx, e, "dtbar copy");
+  return MHD_OK;
+}
+
+mhd_status mhd_adjoint_step_device(mhd_ctx* ctx, const double* U_n, double dt,
+                                   const double* Ubar_np1, double* Ubar_n, double* dtbar_dev,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  return adjoint_impl(ctx, U_n, dt, Ubar_np1, Ubar_n, dtbar_dev != nullptr, dtbar_dev, ws,
+                      ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 mhd_status mhd_check(mhd_ctx* ctx, void* ws, size_t ws_bytes, void* stream) {

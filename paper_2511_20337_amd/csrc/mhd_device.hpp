@@ -54,20 +54,31 @@ __device__ __forceinline__ double rcp_r(double b) {
   e = __builtin_fma(-b, r, 1.0);
   return __builtin_fma(r, e, r);
 }
-__device__ __forceinline__ double div_r(double a, double b) {
-  double r = __builtin_amdgcn_rcp(b);
+// Quotient a/b; r receives the refined reciprocal of b it was formed with.
+__device__ __forceinline__ double div_r_rcp(double a, double b, double& r) {
+  r = __builtin_amdgcn_rcp(b);
   r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
   const double q = a * r;
   return __builtin_fma(__builtin_fma(-b, q, a), r, q);
 }
-__device__ __forceinline__ double sqrt_r(double x) {
+__device__ __forceinline__ double div_r(double a, double b) {
+  double r;
+  return div_r_rcp(a, b, r);
+}
+// Square root of x >= 0; h receives about 1/(2 sqrt(x)) (one Newton step).
+__device__ __forceinline__ double sqrt_r_half(double x, double& h) {
   const double y = __builtin_amdgcn_rsq(x);
-  double h = 0.5 * y, s = x * y;
+  double s = x * y;
+  h = 0.5 * y;
   const double t = __builtin_fma(-s, h, 0.5);
   s = __builtin_fma(s, t, s);
   h = __builtin_fma(h, t, h);
   const double r = __builtin_fma(__builtin_fma(-s, s, x), h, s);
   return x > 0.0 ? r : 0.0;  // the estimate is infinite at 0
+}
+__device__ __forceinline__ double sqrt_r(double x) {
+  double h;
+  return sqrt_r_half(x, h);
 }
 // FP32 (mixed precision): the one-ulp hardware reciprocal and square root.
 __device__ __forceinline__ float rcp_r(float b) {

@@ -39,6 +39,7 @@ static_assert(Tile<2>::NCORE % 64 == 0 && Tile<2>::NCORE <= 1024, "whole wavefro
 // consecutive cells of one row (512 contiguous bytes per field).
 struct RowTile {
   static constexpr int TX = 64, TY = 4, TZ = 1;
+  static constexpr int NT = TX * TY;  // workgroup size
 };
 
 struct MarchGrid {
@@ -139,10 +140,11 @@ __device__ __forceinline__ double emf_comp(const double* __restrict__ U,
 // plane to plane, so each is loaded once per run instead of up to four times.
 struct EmfCol {
   static constexpr int TX = 64, TY = 4;
+  static constexpr int NT = TX * TY;  // workgroup size
 };
 
 template <int LIM, class R>
-__global__ __launch_bounds__(kBlock) void k_emf_march(const double* __restrict__ U,
+__global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restrict__ U,
                                                       const double* __restrict__ FW,
                                                       double* __restrict__ EW, Geom g,
                                                       MarchGrid mg) {
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_emf_march(const double* __restrict__
 }
 
 template <int DIM, int LIM, class R>
-__global__ __launch_bounds__(kBlock) void k_emf(const double* __restrict__ U,
+__global__ __launch_bounds__(RowTile::NT) void k_emf(const double* __restrict__ U,
                                                 const double* __restrict__ FW,
                                                 double* __restrict__ EW, Geom g, TileGrid tg) {
   int i, j, k;
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_emf(const double* __restrict__ U,
 
 // STAGE 0: out = L(U); 1: out = U + dt L(U); 2: out = (U0 + (U + dt L(U))) / 2.
 template <int DIM, int STAGE>
-__global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ U,
+__global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict__ U,
                                                    const double* U0, double* out,
                                                    const double* __restrict__ FW,
                                                    const double* __restrict__ EW, Geom g,
@@ -765,11 +767,11 @@ hipError_t stage_impl(const StageArgs& a) {
     eg.nzc = (a.g.nz + eg.lz - 1) / eg.lz;
     eg.nblocks = (unsigned)eg.ntx * (unsigned)eg.nty * (unsigned)eg.nzc;
     MHD_TIMED(a, K_EMF,
-              hipLaunchKernelGGL((k_emf_march<LIM, R>), dim3(eg.nblocks), dim3(kBlock), 0,
+              hipLaunchKernelGGL((k_emf_march<LIM, R>), dim3(eg.nblocks), dim3(EmfCol::NT), 0,
                                  a.stream, a.U, a.FW, a.EW, a.g, eg));
   } else {
     MHD_TIMED(a, K_EMF,
-              hipLaunchKernelGGL((k_emf<DIM, LIM, R>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,
+              hipLaunchKernelGGL((k_emf<DIM, LIM, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                  a.FW, a.EW, a.g, rg));
   }
   switch (a.stage) {
@@ -777,17 +779,17 @@ hipError_t stage_impl(const StageArgs& a) {
       break;
     case 0:
       MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 0>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,
+                hipLaunchKernelGGL((k_update<DIM, 0>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                    a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
       break;
     case 1:
       MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 1>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,
+                hipLaunchKernelGGL((k_update<DIM, 1>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                    a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
       break;
     default:
       MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 2>), dim3(nb), dim3(kBlock), 0, a.stream, a.U,
+                hipLaunchKernelGGL((k_update<DIM, 2>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                    a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
       break;
   }

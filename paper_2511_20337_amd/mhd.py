@@ -29,7 +29,8 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 
 # Every symbol include/mhd.h declares.
 SYMBOLS = ("mhd_init", "mhd_destroy", "mhd_workspace_bytes", "mhd_dt", "mhd_dt_device",
-           "mhd_step", "mhd_step_device_dt", "mhd_rhs", "mhd_adjoint_step", "mhd_check",
+           "mhd_step", "mhd_step_device_dt", "mhd_rhs", "mhd_adjoint_step",
+           "mhd_adjoint_step_device", "mhd_check",
            "mhd_timing", "mhd_timing_read", "mhd_strerror", "mhd_last_error")
 
 
@@ -78,6 +79,7 @@ def lib():
             "mhd_step_device_dt": ([vp, vp, vp, vp, sz, vp], st),
             "mhd_rhs": ([vp, vp, vp, vp, sz, vp], st),
             "mhd_adjoint_step": ([vp, vp, ctypes.c_double, vp, vp, dp, vp, sz, vp], st),
+            "mhd_adjoint_step_device": ([vp, vp, ctypes.c_double, vp, vp, vp, vp, sz, vp], st),
             "mhd_check": ([vp, vp, sz, vp], st),
             "mhd_timing": ([vp, ctypes.c_int32], st),
             "mhd_timing_read": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p),
@@ -181,6 +183,15 @@ def mhd_adjoint_step(ctx, U_n, dt: float, Ubar_np1, Ubar_n, ws, want_dtbar=False
     return dtbar.value if want_dtbar else None
 
 
+def mhd_adjoint_step_device(ctx, U_n, dt: float, Ubar_np1, Ubar_n, ws, dtbar_dev=None):
+    """dtbar_dev: a float64 device tensor of at least one element (or None)."""
+    ptr = None if dtbar_dev is None else dtbar_dev.data_ptr()
+    rc = lib().mhd_adjoint_step_device(ctx, U_n.data_ptr(), float(dt), Ubar_np1.data_ptr(),
+                                       Ubar_n.data_ptr(), ptr, ws.data_ptr(), ws.numel(),
+                                       _stream(U_n.device))
+    _raise(ctx, rc, "mhd_adjoint_step_device")
+
+
 def mhd_check(ctx, ws, device=None) -> None:
     rc = lib().mhd_check(ctx, ws.data_ptr(), ws.numel(), _stream(device or ws.device))
     _raise(ctx, rc, "mhd_check")
@@ -262,9 +273,20 @@ class Context:
         mhd_rhs(self.ctx, self._state(U), self._state(out), self.ws)
         return out
 
-    def adjoint_step(self, U_n, dt: float, Ubar_np1, want_dtbar=False, out=None):
+    def adjoint_step(self, U_n, dt: float, Ubar_np1, want_dtbar=False, out=None,
+                     dtbar_out=None):
+        """Ubar_n (and dt-bar as a host float with want_dtbar). With dtbar_out
+        (a float64 device tensor), dt-bar is written there without a host
+        synchronisation."""
         import torch
         out = torch.empty_like(Ubar_np1) if out is None else out
+        if dtbar_out is not None:
+            if dtbar_out.dtype != torch.float64 or dtbar_out.device != self.device or \
+                    dtbar_out.numel() < 1:
+                raise MHDError(MHD_ERR_INVALID, "dtbar_out: a float64 tensor on the device")
+            mhd_adjoint_step_device(self.ctx, self._state(U_n), dt, self._state(Ubar_np1),
+                                    self._state(out), self.ws, dtbar_out)
+            return out
         dtbar = mhd_adjoint_step(self.ctx, self._state(U_n), dt, self._state(Ubar_np1),
                                  self._state(out), self.ws, want_dtbar)
         return (out, dtbar) if want_dtbar else out

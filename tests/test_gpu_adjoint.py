@@ -282,3 +282,26 @@ def test_blast_inner_pressure_gradient_vs_central_fd(dev):
           flush=True)
     assert grad == pytest.approx(jv, rel=1e-9), (grad, jv)
     assert err <= 1e-6, (grad, fd, err)
+
+
+def test_adjoint_device_dtbar_matches_host(dev):
+    """mhd_adjoint_step_device (dt-bar left on the device, no synchronisation)
+    gives bit-identical results to mhd_adjoint_step; a null dt-bar pointer
+    still yields Ubar_n."""
+    from paper_2511_20337_amd import mhd
+    s, U = smooth_ragged(3, 12, 10, 11, "vanleer", "hlld", seed=4)
+    ctx = mhd.Context(s, dev, with_adjoint=True)
+    Ug = torch.from_numpy(U).to(dev)
+    ub = torch.from_numpy(np.random.default_rng(3).normal(size=U.shape)).to(dev)
+    dt = O.dt(O.cfg_from(s), U)
+    ref, dref = ctx.adjoint_step(Ug, dt, ub, want_dtbar=True)
+    dbuf = torch.full((3,), -1.0, dtype=torch.float64, device=dev)
+    got = ctx.adjoint_step(Ug, dt, ub, dtbar_out=dbuf[1:2])
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert float(dbuf[1]) == dref
+    assert float(dbuf[0]) == -1.0 and float(dbuf[2]) == -1.0
+    out = torch.empty_like(ub)
+    mhd.mhd_adjoint_step_device(ctx.ctx, Ug, dt, ub, out, ctx.ws, None)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
