@@ -64,6 +64,9 @@ __device__ __forceinline__ Dual sqrt_r(Dual x) {
   return Dual(s, s > 0.0 ? x.d * h : 0.0);
 }
 __device__ __forceinline__ Dual abs_r(Dual x) { return x.v < 0.0 ? -x : x; }
+__device__ __forceinline__ Dual fma_r(Dual a, Dual b, Dual c) {
+  return Dual(__builtin_fma(a.v, b.v, c.v), __builtin_fma(a.d, b.v, __builtin_fma(a.v, b.d, c.d)));
+}
 __device__ __forceinline__ Dual rcp_r(Dual x) {
   const double r = ::mhd::rcp_r(x.v);
   return Dual(r, -x.d * r * r);

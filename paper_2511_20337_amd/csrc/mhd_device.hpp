@@ -80,6 +80,14 @@ __device__ __forceinline__ double sqrt_r(double x) {
   double h;
   return sqrt_r_half(x, h);
 }
+// a * b + c with one rounding. With contraction off, these are the only fused
+// multiply-adds; the adjoint's dual numbers overload fma_r with the same value.
+__device__ __forceinline__ double fma_r(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fma_r(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
 // FP32 (mixed precision): the one-ulp hardware reciprocal and square root.
 __device__ __forceinline__ float rcp_r(float b) {
   const float r = __builtin_amdgcn_rcpf(b);
@@ -119,9 +127,10 @@ template <class R> struct RiemannOut {
 template <class R>
 __device__ __forceinline__ R cfast(R g, R rho, R p, R bn, R b1, R b2) {
   const R gp = g * p;
-  const R bb = bn * bn + b1 * b1 + b2 * b2;
+  const R bn2 = bn * bn;
+  const R bb = fma_r(b2, b2, fma_r(b1, b1, bn2));
   const R a = gp + bb;
-  const R disc = max_r(R(0), a * a - R(4) * gp * (bn * bn));
+  const R disc = max_r(R(0), fma_r(a, a, -(R(4) * gp) * bn2));
   return sqrt_r(div_r(a + sqrt_r(disc), R(2) * rho));
 }
 
@@ -129,19 +138,20 @@ __device__ __forceinline__ R cfast(R g, R rho, R p, R bn, R b1, R b2) {
 template <class R>
 __device__ __forceinline__ void phys(R igm1, const R* w, R bn, R* u, R* f, R& pt) {
   const R rho = w[0], vn = w[1], v1 = w[2], v2 = w[3], b1 = w[4], b2 = w[5], p = w[6];
-  const R bb = bn * bn + b1 * b1 + b2 * b2;
-  pt = p + R(0.5) * bb;
-  const R en = p * igm1 + R(0.5) * rho * (vn * vn + v1 * v1 + v2 * v2) + R(0.5) * bb;
+  const R bb = fma_r(b2, b2, fma_r(b1, b1, bn * bn));
+  pt = fma_r(R(0.5), bb, p);
+  const R v2s = fma_r(v2, v2, fma_r(v1, v1, vn * vn));
+  const R en = fma_r(R(0.5), bb, fma_r(R(0.5) * rho, v2s, p * igm1));
   const R mn = rho * vn;
   u[0] = rho; u[1] = mn; u[2] = rho * v1; u[3] = rho * v2; u[4] = b1; u[5] = b2; u[6] = en;
-  const R vb = vn * bn + v1 * b1 + v2 * b2;
+  const R vb = fma_r(v2, b2, fma_r(v1, b1, vn * bn));
   f[0] = mn;
-  f[1] = mn * vn + pt - bn * bn;
-  f[2] = mn * v1 - bn * b1;
-  f[3] = mn * v2 - bn * b2;
-  f[4] = vn * b1 - v1 * bn;
-  f[5] = vn * b2 - v2 * bn;
-  f[6] = (en + pt) * vn - bn * vb;
+  f[1] = fma_r(mn, vn, fma_r(-bn, bn, pt));
+  f[2] = fma_r(mn, v1, -bn * b1);
+  f[3] = fma_r(mn, v2, -bn * b2);
+  f[4] = fma_r(vn, b1, -v1 * bn);
+  f[5] = fma_r(vn, b2, -v2 * bn);
+  f[6] = fma_r(en + pt, vn, -bn * vb);
 }
 
 // Relative tolerance below which the HLLD star state is treated as
@@ -172,8 +182,8 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
   o.am = max_r(R(0), -sl);
   {
     const R isum = rcp_r(o.ap + o.am);
-    o.v1 = (o.ap * wl[2] + o.am * wr[2]) * isum;
-    o.v2 = (o.ap * wl[3] + o.am * wr[3]) * isum;
+    o.v1 = fma_r(o.ap, wl[2], o.am * wr[2]) * isum;
+    o.v2 = fma_r(o.ap, wl[3], o.am * wr[3]) * isum;
   }
   if (RS == 1) {
     if (sl >= R(0)) {
@@ -185,7 +195,8 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
     } else {
       const R idn = rcp_r(sr - sl);
 #pragma unroll
-      for (int q = 0; q < 7; ++q) o.f[q] = (sr * fl[q] - sl * fr[q] + sl * sr * (ur[q] - ul[q])) * idn;
+      for (int q = 0; q < 7; ++q)
+        o.f[q] = fma_r(sl * sr, ur[q] - ul[q], fma_r(sr, fl[q], -sl * fr[q])) * idn;
     }
     return;
   }
@@ -202,8 +213,8 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
   const R dl = sl - wl[1], dr = sr - wr[1];
   const R ml = dl * wl[0], mr = dr * wr[0];          // mass fluxes through the outer fronts
   const R iden = rcp_r(mr - ml);
-  const R sm = (mr * wr[1] - ml * wl[1] - ptr + ptl) * iden;
-  const R pts = (mr * ptl - ml * ptr + ml * mr * (wr[1] - wl[1])) * iden;
+  const R sm = fma_r(mr, wr[1], fma_r(-ml, wl[1], ptl - ptr)) * iden;
+  const R pts = fma_r(ml * mr, wr[1] - wl[1], fma_r(mr, ptl, -ml * ptr)) * iden;
   const R bn2 = bn * bn;
 
   // star states, one side at a time: s = 0 left, 1 right
@@ -225,15 +236,15 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
     } else {
       const R iden2 = rcp_r(den);
       const R fv = bn * (sm - w[1]) * iden2;
-      vs[s] = w[2] - w[4] * fv;
-      ws[s] = w[3] - w[5] * fv;
-      const R fb = (m * d - bn2) * iden2;
+      vs[s] = fma_r(-w[4], fv, w[2]);
+      ws[s] = fma_r(-w[5], fv, w[3]);
+      const R fb = fma_r(m, d, -bn2) * iden2;
       b1s[s] = w[4] * fb;
       b2s[s] = w[5] * fb;
     }
-    const R vb = w[1] * bn + w[2] * w[4] + w[3] * w[5];
-    const R vbs = sm * bn + vs[s] * b1s[s] + ws[s] * b2s[s];
-    es[s] = (d * en - pt * w[1] + pts * sm + bn * (vb - vbs)) * ism;
+    const R vb = fma_r(w[3], w[5], fma_r(w[2], w[4], w[1] * bn));
+    const R vbs = fma_r(ws[s], b2s[s], fma_r(vs[s], b1s[s], sm * bn));
+    es[s] = fma_r(bn, vb - vbs, fma_r(pts, sm, fma_r(d, en, -pt * w[1]))) * ism;
   }
   const R sql = sqrt_r(rs[0]), sqr = sqrt_r(rs[1]);
   const R abn = abs_r(bn);
@@ -243,40 +254,41 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
   if (sls >= R(0)) {  // F*_L
     const R us[7] = {rs[0], rs[0] * sm, rs[0] * vs[0], rs[0] * ws[0], b1s[0], b2s[0], es[0]};
 #pragma unroll
-    for (int q = 0; q < 7; ++q) o.f[q] = fl[q] + sl * (us[q] - ul[q]);
+    for (int q = 0; q < 7; ++q) o.f[q] = fma_r(sl, us[q] - ul[q], fl[q]);
     return;
   }
   const R sgn = (bn > R(0)) ? R(1) : ((bn < R(0)) ? R(-1) : R(0));
   const R isq = rcp_r(sql + sqr);
-  const R vss = (sql * vs[0] + sqr * vs[1] + sgn * (b1s[1] - b1s[0])) * isq;
-  const R wss = (sql * ws[0] + sqr * ws[1] + sgn * (b2s[1] - b2s[0])) * isq;
-  const R b1ss = (sql * b1s[1] + sqr * b1s[0] + sgn * sql * sqr * (vs[1] - vs[0])) * isq;
-  const R b2ss = (sql * b2s[1] + sqr * b2s[0] + sgn * sql * sqr * (ws[1] - ws[0])) * isq;
-  const R vbss = vss * b1ss + wss * b2ss;
+  const R ssq = sgn * sql * sqr;
+  const R vss = fma_r(sgn, b1s[1] - b1s[0], fma_r(sql, vs[0], sqr * vs[1])) * isq;
+  const R wss = fma_r(sgn, b2s[1] - b2s[0], fma_r(sql, ws[0], sqr * ws[1])) * isq;
+  const R b1ss = fma_r(ssq, vs[1] - vs[0], fma_r(sql, b1s[1], sqr * b1s[0])) * isq;
+  const R b2ss = fma_r(ssq, ws[1] - ws[0], fma_r(sql, b2s[1], sqr * b2s[0])) * isq;
+  const R vbss = fma_r(vss, b1ss, wss * b2ss);
   if (sm >= R(0)) {  // F**_L
-    const R ess = es[0] - sgn * sql * ((vs[0] * b1s[0] + ws[0] * b2s[0]) - vbss);
+    const R ess = fma_r(-sgn * sql, fma_r(vs[0], b1s[0], ws[0] * b2s[0]) - vbss, es[0]);
     const R us[7] = {rs[0], rs[0] * sm, rs[0] * vs[0], rs[0] * ws[0], b1s[0], b2s[0], es[0]};
     const R uss[7] = {rs[0], rs[0] * sm, rs[0] * vss, rs[0] * wss, b1ss, b2ss, ess};
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-      const R fs = fl[q] + sl * (us[q] - ul[q]);
-      o.f[q] = fs + sls * (uss[q] - us[q]);
+      const R fs = fma_r(sl, us[q] - ul[q], fl[q]);
+      o.f[q] = fma_r(sls, uss[q] - us[q], fs);
     }
     return;
   }
   const R us[7] = {rs[1], rs[1] * sm, rs[1] * vs[1], rs[1] * ws[1], b1s[1], b2s[1], es[1]};
   if (srs >= R(0)) {  // F**_R
-    const R ess = es[1] + sgn * sqr * ((vs[1] * b1s[1] + ws[1] * b2s[1]) - vbss);
+    const R ess = fma_r(sgn * sqr, fma_r(vs[1], b1s[1], ws[1] * b2s[1]) - vbss, es[1]);
     const R uss[7] = {rs[1], rs[1] * sm, rs[1] * vss, rs[1] * wss, b1ss, b2ss, ess};
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-      const R fs = fr[q] + sr * (us[q] - ur[q]);
-      o.f[q] = fs + srs * (uss[q] - us[q]);
+      const R fs = fma_r(sr, us[q] - ur[q], fr[q]);
+      o.f[q] = fma_r(srs, uss[q] - us[q], fs);
     }
     return;
   }
 #pragma unroll
-  for (int q = 0; q < 7; ++q) o.f[q] = fr[q] + sr * (us[q] - ur[q]);  // F*_R
+  for (int q = 0; q < 7; ++q) o.f[q] = fma_r(sr, us[q] - ur[q], fr[q]);  // F*_R
 }
 
 // Upwind edge EMF for component c with cyclic pair (a, b); the exact value
@@ -296,8 +308,8 @@ __device__ __forceinline__ R uct(R apa, R ama, R vW, R bW, R vE, R bE,
 // hi = x(0) - slope(0)/2, from the four faces x(-2), x(-1), x(0), x(+1).
 template <int LIM, class R>
 __device__ __forceinline__ void edge_pair(R xm2, R xm1, R x0, R xp1, R& lo, R& hi) {
-  lo = xm1 + R(0.5) * plm_slope<LIM, R>(xm1 - xm2, x0 - xm1);
-  hi = x0 - R(0.5) * plm_slope<LIM, R>(x0 - xm1, xp1 - x0);
+  lo = fma_r(R(0.5), plm_slope<LIM, R>(xm1 - xm2, x0 - xm1), xm1);
+  hi = fma_r(R(-0.5), plm_slope<LIM, R>(x0 - xm1, xp1 - x0), x0);
 }
 
 }  // namespace mhd

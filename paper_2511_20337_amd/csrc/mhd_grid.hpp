@@ -61,8 +61,8 @@ __device__ __forceinline__ bool prim_from_raw(const RawCell& r, double gamma, do
   const double bz = (DIM == 3) ? 0.5 * (r.u[7] + r.bzp) : r.u[7];
   const double irho = 1.0 / rho;
   const double vx = mx * irho, vy = my * irho, vz = mz * irho;
-  const double kin = 0.5 * (mx * vx + my * vy + mz * vz);
-  const double mag = 0.5 * (bx * bx + by * by + bz * bz);
+  const double kin = 0.5 * fma_r(mz, vz, fma_r(my, vy, mx * vx));
+  const double mag = 0.5 * fma_r(bz, bz, fma_r(by, by, bx * bx));
   const double p = (gamma - 1.0) * (en - kin - mag);
   V[0] = rho; V[1] = vx; V[2] = vy; V[3] = vz; V[4] = p; V[5] = bx; V[6] = by; V[7] = bz;
   return (rho > 0.0) && (p > 0.0) && __builtin_isfinite(p) && __builtin_isfinite(vx) &&
@@ -95,8 +95,8 @@ __device__ __forceinline__ void face_inputs(const double* __restrict__ U, const 
   for (int q = 0; q < 7; ++q) {
     const int s = slot[q];
     const double a = V[0][s], b = V[1][s], c = V[2][s], e = V[3][s];
-    wl[q] = b + 0.5 * plm_slope<LIM, double>(b - a, c - b);
-    wr[q] = c - 0.5 * plm_slope<LIM, double>(c - b, e - c);
+    wl[q] = fma_r(0.5, plm_slope<LIM, double>(b - a, c - b), b);
+    wr[q] = fma_r(-0.5, plm_slope<LIM, double>(c - b, e - c), c);
   }
   bn = U[(F_BX + D) * g.n + lin(g, i, j, k)];
 }

@@ -369,8 +369,8 @@ __device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM],
   for (int q = 0; q < 7; ++q) {
     const R* P = sp[slot[q]];
     const R a = P[e[0]], b = P[e[1]], cc = P[e[2]], d = P[e[3]];
-    wl[q] = b + R(0.5) * plm_slope<LIM, R>(b - a, cc - b);
-    wr[q] = cc - R(0.5) * plm_slope<LIM, R>(cc - b, d - cc);
+    wl[q] = fma_r(R(0.5), plm_slope<LIM, R>(b - a, cc - b), b);
+    wr[q] = fma_r(R(-0.5), plm_slope<LIM, R>(cc - b, d - cc), cc);
   }
   const R bn = (R)U[(F_BX + D) * g.n + c];
   RiemannOut<R> o;
@@ -550,8 +550,8 @@ __device__ __forceinline__ void march_face_xy(const R* lds, const int* o, const 
     R v[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = (sq == 7) ? lds[ob[s]] : lds[o[s] + sq * st[s]];
-    wl[q] = v[1] + R(0.5) * plm_slope<LIM, R>(v[1] - v[0], v[2] - v[1]);
-    wr[q] = v[2] - R(0.5) * plm_slope<LIM, R>(v[2] - v[1], v[3] - v[2]);
+    wl[q] = fma_r(R(0.5), plm_slope<LIM, R>(v[1] - v[0], v[2] - v[1]), v[1]);
+    wr[q] = fma_r(R(-0.5), plm_slope<LIM, R>(v[2] - v[1], v[3] - v[2]), v[2]);
   }
   march_solve<D, RS, R>(wl, wr, bn, FW, g, c);
 }
@@ -596,7 +596,7 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const int sq = zslot[q];
-      zl[q] = Vm1[sq] + R(0.5) * plm_slope<LIM, R>(Vm1[sq] - Vm2[sq], V0[sq] - Vm1[sq]);
+      zl[q] = fma_r(R(0.5), plm_slope<LIM, R>(Vm1[sq] - Vm2[sq], V0[sq] - Vm1[sq]), Vm1[sq]);
     }
     if (haloer) {
       R H[8];
@@ -643,8 +643,8 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
         const R cc = lds[rp * kRingP + sq * kRingQ + cidx];
         const R dlt = plm_slope<LIM, R>(bb - a, cc - bb);
         wl[q] = zl[q];
-        wr[q] = bb - R(0.5) * dlt;
-        zl[q] = bb + R(0.5) * dlt;
+        wr[q] = fma_r(R(-0.5), dlt, bb);
+        zl[q] = fma_r(R(0.5), dlt, bb);
       }
       march_solve<2, RS, R>(wl, wr, (R)bnz, FW, g, c);
     }
