@@ -49,7 +49,7 @@ KERNEL_BOUND = {"faces": "alu", "emf": "hbm", "update": "hbm", "cfl": "hbm"}
 # HBM bytes per cell of one launch measured with rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.0 and 1.0), for the
 # kernels as they stand; see profiles/.
-KERNEL_TRAFFIC = {"faces": 202.3 + 216.0}
+KERNEL_TRAFFIC = {"faces": 202.0 + 216.0}
 
 
 def time_gpu(setup, U0, steps, warmup, timing=True):
