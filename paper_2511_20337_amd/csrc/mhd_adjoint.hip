@@ -13,8 +13,8 @@
 //                 of alpha+-, the weighted velocities and b gathered from the
 //                 edges that used them (through the adjoint of their
 //                 reconstruction), then the Riemann solver's vector-Jacobian
-//                 product, evaluated with the solver itself on a forward-mode
-//                 dual scalar, one pass per input;
+//                 product: one hand-written reverse sweep over the values the
+//                 solver itself recorded;
 //   k_adj_cells — per cell: adjoint of PLM (gathering the face-state
 //                 cotangents of the faces each cell feeds) and of primitive
 //                 recovery;
@@ -31,50 +31,374 @@ namespace mhd {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Forward-mode dual scalar (value, one tangent) for the Riemann solver.
-struct Dual {
-  double v, d;
-  __device__ __forceinline__ Dual() : v(0.0), d(0.0) {}
-  __device__ __forceinline__ Dual(double x) : v(x), d(0.0) {}  // NOLINT
-  __device__ __forceinline__ Dual(double x, double t) : v(x), d(t) {}
+// Hand-written reverse sweep of the Riemann solver. The forward values come
+// from riemann_core itself (recorded on a tape), so every branch (wave-speed
+// min/max, HLL/HLLD region, degenerate star state, sign of the normal field)
+// is the one the forward kernels take; the derivative of each recorded
+// branch is then propagated backwards once for all fifteen inputs. At a
+// square root of zero the derivative is taken as zero.
+
+// phys(): cotangents of u[7], f[7] and pt -> added to wb[7] and bnb.
+__device__ __forceinline__ void phys_vjp(double igm1, const double* w, double bn,
+                                         const double* ub, const double* fb, double ptb,
+                                         double* wb, double& bnb) {
+  const double rho = w[0], vn = w[1], v1 = w[2], v2 = w[3], b1 = w[4], b2 = w[5], p = w[6];
+  const double bb = bn * bn + b1 * b1 + b2 * b2;
+  const double pt = p + 0.5 * bb;
+  const double v2s = vn * vn + v1 * v1 + v2 * v2;
+  const double en = p * igm1 + 0.5 * rho * v2s + 0.5 * bb;
+  const double mn = rho * vn;
+  const double vb = vn * bn + v1 * b1 + v2 * b2;
+  double mnb = fb[0] + fb[1] * vn + fb[2] * v1 + fb[3] * v2 + ub[1];
+  double vnb = fb[1] * mn + fb[4] * b1 + fb[5] * b2 + fb[6] * (en + pt);
+  double v1b = fb[2] * mn - fb[4] * bn + ub[2] * rho;
+  double v2b = fb[3] * mn - fb[5] * bn + ub[3] * rho;
+  double b1b = -fb[2] * bn + fb[4] * vn + ub[4];
+  double b2b = -fb[3] * bn + fb[5] * vn + ub[5];
+  double bnl = -2.0 * bn * fb[1] - fb[2] * b1 - fb[3] * b2 - fb[4] * v1 - fb[5] * v2 - fb[6] * vb;
+  const double ptt = ptb + fb[1] + fb[6] * vn;
+  const double enb = ub[6] + fb[6] * vn;
+  const double vbb = -fb[6] * bn;
+  vnb += vbb * bn;
+  bnl += vbb * vn;
+  v1b += vbb * b1;
+  b1b += vbb * v1;
+  v2b += vbb * b2;
+  b2b += vbb * v2;
+  const double rhob = ub[0] + ub[2] * v1 + ub[3] * v2 + mnb * vn + enb * 0.5 * v2s;
+  vnb += mnb * rho;
+  const double v2sb = enb * 0.5 * rho;
+  const double bbb = 0.5 * (enb + ptt);
+  const double pb = enb * igm1 + ptt;
+  vnb += 2.0 * vn * v2sb;
+  v1b += 2.0 * v1 * v2sb;
+  v2b += 2.0 * v2 * v2sb;
+  bnl += 2.0 * bn * bbb;
+  b1b += 2.0 * b1 * bbb;
+  b2b += 2.0 * b2 * bbb;
+  wb[0] += rhob; wb[1] += vnb; wb[2] += v1b; wb[3] += v2b; wb[4] += b1b; wb[5] += b2b;
+  wb[6] += pb;
+  bnb += bnl;
+}
+
+// cfast(): cotangent of c_f -> added to rho, p (wb[0], wb[6]), b_t (wb[4], wb[5]), bn.
+// The branch values are recomputed with cfast's own expressions.
+__device__ __forceinline__ void cfast_vjp(double g, const double* w, double bn, double cfb,
+                                          double* wb, double& bnb) {
+  const double rho = w[0], p = w[6], b1 = w[4], b2 = w[5];
+  const double gp = g * p;
+  const double bn2 = bn * bn;
+  const double bb = fma_r(b2, b2, fma_r(b1, b1, bn2));
+  const double a = gp + bb;
+  const double x = fma_r(a, a, -(4.0 * gp) * bn2);
+  const double disc = max_r(0.0, x);
+  const double sd = sqrt_r(disc);
+  const double q = div_r(a + sd, 2.0 * rho);
+  const double cf = sqrt_r(q);
+  const double qb = cf > 0.0 ? cfb * 0.5 / cf : 0.0;
+  const double i2r = 0.5 / rho;
+  double ab = qb * i2r;
+  const double sdb = qb * i2r;
+  const double rhob = -qb * q / rho;
+  const double discb = sd > 0.0 ? sdb * 0.5 / sd : 0.0;
+  const double xb = (x > 0.0) ? discb : 0.0;
+  ab += 2.0 * a * xb;
+  const double gpb = -4.0 * bn2 * xb + ab;
+  const double bn2b = -4.0 * gp * xb + ab;
+  wb[0] += rhob;
+  wb[6] += g * gpb;
+  wb[4] += 2.0 * b1 * ab;
+  wb[5] += 2.0 * b2 * ab;
+  bnb += 2.0 * bn * bn2b;
+}
+
+// Cotangents of the star state U*_s = (rho*, rho* S_M, rho* v*, rho* w*,
+// B*_t1, B*_t2, E*) of side s -> the per-side adjoint accumulators.
+struct StarBar {
+  double rs[2], vs[2], ws[2], b1s[2], b2s[2], es[2];
+  double sm;
 };
-__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
-__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
-__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
-__device__ __forceinline__ Dual operator*(Dual a, Dual b) {
-  return Dual(a.v * b.v, __builtin_fma(a.d, b.v, a.v * b.d));
+
+__device__ __forceinline__ void star_us_vjp(const RiemannTape& t, int s, const double* usb,
+                                            StarBar& sb) {
+  sb.rs[s] += usb[0] + usb[1] * t.sm + usb[2] * t.vs[s] + usb[3] * t.ws[s];
+  sb.sm += usb[1] * t.rs[s];
+  sb.vs[s] += usb[2] * t.rs[s];
+  sb.ws[s] += usb[3] * t.rs[s];
+  sb.b1s[s] += usb[4];
+  sb.b2s[s] += usb[5];
+  sb.es[s] += usb[6];
 }
-__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
-  const double q = a.v / b.v;
-  return Dual(q, (a.d - q * b.d) / b.v);
-}
-__device__ __forceinline__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
-__device__ __forceinline__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
-__device__ __forceinline__ bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
-__device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
-// Found by argument-dependent lookup from the solver template. The value
-// parts use the same quotient, reciprocal and square root as the forward
-// kernels, so a dual pass reproduces the forward values bit for bit and
-// takes the same branches.
-// (Tangents may round differently from their exact quotients; only the
-// values steer branches.)
-__device__ __forceinline__ Dual sqrt_r(Dual x) {
-  double h;
-  const double s = ::mhd::sqrt_r_half(x.v, h);
-  return Dual(s, s > 0.0 ? x.d * h : 0.0);
-}
-__device__ __forceinline__ Dual abs_r(Dual x) { return x.v < 0.0 ? -x : x; }
-__device__ __forceinline__ Dual fma_r(Dual a, Dual b, Dual c) {
-  return Dual(__builtin_fma(a.v, b.v, c.v), __builtin_fma(a.d, b.v, __builtin_fma(a.v, b.d, c.d)));
-}
-__device__ __forceinline__ Dual rcp_r(Dual x) {
-  const double r = ::mhd::rcp_r(x.v);
-  return Dual(r, -x.d * r * r);
-}
-__device__ __forceinline__ Dual div_r(Dual a, Dual b) {
-  double r;
-  const double q = ::mhd::div_r_rcp(a.v, b.v, r);
-  return Dual(q, __builtin_fma(-q, b.d, a.d) * r);
+
+template <int RS>
+__device__ __forceinline__ void riemann_vjp(double g, const double* wl, const double* wr, double bn,
+                                            const double* fbar, double apbar, double ambar,
+                                            double v1bar, double v2bar, double* wlb, double* wrb,
+                                            double& bnb) {
+  RiemannTape t;
+  RiemannOut<double> o;
+  riemann_core<RS, double, RiemannTape>(g, wl, wr, bn, o, t);
+  const double igm1 = rcp_r(g - 1.0);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) { wlb[q] = 0.0; wrb[q] = 0.0; }
+  bnb = 0.0;
+  double ulb[7], flb[7], urb[7], frb[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) { ulb[q] = 0.0; flb[q] = 0.0; urb[q] = 0.0; frb[q] = 0.0; }
+  double ptlb = 0.0, ptrb = 0.0, slb = 0.0, srb = 0.0;
+  // HLL-weighted velocities v = (ap wl + am wr) / (ap + am)
+  const double n1b = v1bar * t.isum, n2b = v2bar * t.isum;
+  const double sumb = -(v1bar * t.v1 + v2bar * t.v2) * t.isum;
+  const double apb = apbar + n1b * wl[2] + n2b * wl[3] + sumb;
+  const double amb = ambar + n1b * wr[2] + n2b * wr[3] + sumb;
+  wlb[2] += n1b * t.ap;
+  wrb[2] += n1b * t.am;
+  wlb[3] += n2b * t.ap;
+  wrb[3] += n2b * t.am;
+  const int reg = t.region;
+  if (reg == 0) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) flb[q] += fbar[q];
+  } else if (reg == 1) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) frb[q] += fbar[q];
+  } else if (RS == 1) {
+    // HLL fan: f = (sl sr (ur - ul) + sr fl - sl fr) / (sr - sl)
+    double db = 0.0;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const double nb = fbar[q] * t.idn;
+      db -= fbar[q] * o.f[q] * t.idn;
+      const double du = t.ur[q] - t.ul[q];
+      slb += nb * (t.sr * du - t.fr[q]);
+      srb += nb * (t.sl * du + t.fl[q]);
+      urb[q] += nb * t.sl * t.sr;
+      ulb[q] -= nb * t.sl * t.sr;
+      flb[q] += nb * t.sr;
+      frb[q] -= nb * t.sl;
+    }
+    srb += db;
+    slb -= db;
+  } else {
+    // HLLD fan
+    StarBar sb;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      sb.rs[q] = 0.0; sb.vs[q] = 0.0; sb.ws[q] = 0.0; sb.b1s[q] = 0.0; sb.b2s[q] = 0.0;
+      sb.es[q] = 0.0;
+    }
+    sb.sm = 0.0;
+    double ptsb = 0.0, slsb = 0.0, srsb = 0.0, sqlb = 0.0, sqrb = 0.0;
+    const int side = (reg == 3 || reg == 4) ? 0 : 1;
+    const double S = side ? t.sr : t.sl;
+    const double* uo = side ? t.ur : t.ul;
+    double* uob = side ? urb : ulb;
+    double* fob = side ? frb : flb;
+    const double us[7] = {t.rs[side], t.rs[side] * t.sm, t.rs[side] * t.vs[side],
+                          t.rs[side] * t.ws[side], t.b1s[side], t.b2s[side], t.es[side]};
+    double usb[7];
+    double Sb = 0.0;
+    if (reg == 3 || reg == 6) {
+      // F*_a = F_a + S_a (U*_a - U_a)
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        fob[q] += fbar[q];
+        Sb += fbar[q] * (us[q] - uo[q]);
+        usb[q] = fbar[q] * S;
+        uob[q] -= fbar[q] * S;
+      }
+    } else {
+      // F**_a = F*_a + S*_a (U**_a - U*_a)
+      const double sa = side ? t.srs : t.sls;
+      const double uss[7] = {t.rs[side], t.rs[side] * t.sm, t.rs[side] * t.vss,
+                             t.rs[side] * t.wss, t.b1ss, t.b2ss, t.ess};
+      double ussb[7], sab = 0.0;
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        sab += fbar[q] * (uss[q] - us[q]);
+        ussb[q] = fbar[q] * sa;
+        usb[q] = -fbar[q] * sa + fbar[q] * S;
+        Sb += fbar[q] * (us[q] - uo[q]);
+        uob[q] -= fbar[q] * S;
+        fob[q] += fbar[q];
+      }
+      if (side) srsb += sab; else slsb += sab;
+      // U** of this side
+      sb.rs[side] += ussb[0] + ussb[1] * t.sm + ussb[2] * t.vss + ussb[3] * t.wss;
+      sb.sm += ussb[1] * t.rs[side];
+      double vssb = ussb[2] * t.rs[side], wssb = ussb[3] * t.rs[side];
+      double b1ssb = ussb[4], b2ssb = ussb[5];
+      const double essb = ussb[6];
+      // E**_a = E*_a -+ sgn sq_a ((v*_a B*_1a + w*_a B*_2a) - vbss)
+      sb.es[side] += essb;
+      const double tt = t.vs[side] * t.b1s[side] + t.ws[side] * t.b2s[side] - t.vbss;
+      const double sqa = side ? t.sqr : t.sql;
+      const double cc = side ? t.sgn * sqa : -t.sgn * sqa;
+      const double ttb = essb * cc;
+      const double sqab = essb * tt * (side ? t.sgn : -t.sgn);
+      if (side) sqrb += sqab; else sqlb += sqab;
+      sb.vs[side] += ttb * t.b1s[side];
+      sb.b1s[side] += ttb * t.vs[side];
+      sb.ws[side] += ttb * t.b2s[side];
+      sb.b2s[side] += ttb * t.ws[side];
+      const double vbssb = -ttb;
+      // vbss = vss b1ss + wss b2ss
+      vssb += vbssb * t.b1ss;
+      b1ssb += vbssb * t.vss;
+      wssb += vbssb * t.b2ss;
+      b2ssb += vbssb * t.wss;
+      // double-star v, w, B_t: (... ) * isq
+      const double nv = t.sql * t.vs[0] + t.sqr * t.vs[1] + t.sgn * (t.b1s[1] - t.b1s[0]);
+      const double nw = t.sql * t.ws[0] + t.sqr * t.ws[1] + t.sgn * (t.b2s[1] - t.b2s[0]);
+      const double nb1 = t.sql * t.b1s[1] + t.sqr * t.b1s[0] + t.ssq * (t.vs[1] - t.vs[0]);
+      const double nb2 = t.sql * t.b2s[1] + t.sqr * t.b2s[0] + t.ssq * (t.ws[1] - t.ws[0]);
+      const double isqb = vssb * nv + wssb * nw + b1ssb * nb1 + b2ssb * nb2;
+      const double nvb = vssb * t.isq, nwb = wssb * t.isq;
+      const double nb1b = b1ssb * t.isq, nb2b = b2ssb * t.isq;
+      sqlb += nvb * t.vs[0] + nwb * t.ws[0] + nb1b * t.b1s[1] + nb2b * t.b2s[1];
+      sqrb += nvb * t.vs[1] + nwb * t.ws[1] + nb1b * t.b1s[0] + nb2b * t.b2s[0];
+      sb.vs[0] += nvb * t.sql - nb1b * t.ssq;
+      sb.vs[1] += nvb * t.sqr + nb1b * t.ssq;
+      sb.ws[0] += nwb * t.sql - nb2b * t.ssq;
+      sb.ws[1] += nwb * t.sqr + nb2b * t.ssq;
+      sb.b1s[1] += nvb * t.sgn + nb1b * t.sql;
+      sb.b1s[0] += -nvb * t.sgn + nb1b * t.sqr;
+      sb.b2s[1] += nwb * t.sgn + nb2b * t.sql;
+      sb.b2s[0] += -nwb * t.sgn + nb2b * t.sqr;
+      const double ssqb = nb1b * (t.vs[1] - t.vs[0]) + nb2b * (t.ws[1] - t.ws[0]);
+      sqlb += ssqb * t.sgn * t.sqr;
+      sqrb += ssqb * t.sgn * t.sql;
+      const double sumq = -isqb * t.isq * t.isq;
+      sqlb += sumq;
+      sqrb += sumq;
+    }
+    star_us_vjp(t, side, usb, sb);
+    if (side) srb += Sb; else slb += Sb;
+    // Alfven fronts S*_L = S_M - |bn|/sql, S*_R = S_M + |bn|/sqr
+    {
+      sb.sm += slsb + srsb;
+      const double ql = t.abn / t.sql, qr = t.abn / t.sqr;
+      const double abnb = -slsb / t.sql + srsb / t.sqr;
+      sqlb += slsb * ql / t.sql;
+      sqrb -= srsb * qr / t.sqr;
+      bnb += abnb * (bn < 0.0 ? -1.0 : 1.0);
+      sb.rs[0] += t.sql > 0.0 ? sqlb * 0.5 / t.sql : 0.0;
+      sb.rs[1] += t.sqr > 0.0 ? sqrb * 0.5 / t.sqr : 0.0;
+    }
+    // star states of both sides
+    double bn2b = 0.0, mlb = 0.0, mrb = 0.0, dlb = 0.0, drb = 0.0;
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const double* w = sd ? wr : wl;
+      double* wb = sd ? wrb : wlb;
+      const double d = sd ? t.dr : t.dl;
+      const double m = sd ? t.mr : t.ml;
+      const double Sv = sd ? t.sr : t.sl;
+      const double pt = sd ? t.ptr : t.ptl;
+      const double en = sd ? t.ur[6] : t.ul[6];
+      const double ne = d * en - pt * w[1] + t.pts * t.sm + bn * (t.vb[sd] - t.vbs[sd]);
+      const double neb = sb.es[sd] * t.ism[sd];
+      double ismb = sb.es[sd] * ne;
+      double db_ = neb * en;
+      const double enb = neb * d;
+      const double ptb = -neb * w[1];
+      wb[1] -= neb * pt;
+      ptsb += neb * t.sm;
+      sb.sm += neb * t.pts;
+      bnb += neb * (t.vb[sd] - t.vbs[sd]);
+      const double vbb = neb * bn, vbsb = -neb * bn;
+      sb.sm += vbsb * bn;
+      bnb += vbsb * t.sm;
+      double vsb = sb.vs[sd] + vbsb * t.b1s[sd];
+      double b1sb = sb.b1s[sd] + vbsb * t.vs[sd];
+      double wsb = sb.ws[sd] + vbsb * t.b2s[sd];
+      double b2sb = sb.b2s[sd] + vbsb * t.ws[sd];
+      wb[1] += vbb * bn;
+      bnb += vbb * w[1];
+      wb[2] += vbb * w[4];
+      wb[4] += vbb * w[2];
+      wb[3] += vbb * w[5];
+      wb[5] += vbb * w[3];
+      double mb = 0.0, Sbv = 0.0, bigb = 0.0;
+      if (t.deg[sd]) {
+        wb[2] += vsb;
+        wb[3] += wsb;
+        wb[4] += b1sb;
+        wb[5] += b2sb;
+      } else {
+        const double fbk = t.fb[sd], fv = t.fv[sd], iden2 = t.iden2[sd];
+        wb[4] += b1sb * fbk;
+        wb[5] += b2sb * fbk;
+        const double fbb = b1sb * w[4] + b2sb * w[5];
+        const double nfb = fbb * iden2;
+        double iden2b = fbb * (m * d - bn * bn);
+        mb += nfb * d;
+        db_ += nfb * m;
+        bn2b -= nfb;
+        wb[2] += vsb;
+        wb[4] -= vsb * fv;
+        wb[3] += wsb;
+        wb[5] -= wsb * fv;
+        const double fvb = -vsb * w[4] - wsb * w[5];
+        bnb += fvb * (t.sm - w[1]) * iden2;
+        sb.sm += fvb * bn * iden2;
+        wb[1] -= fvb * bn * iden2;
+        iden2b += fvb * bn * (t.sm - w[1]);
+        const double denb = -iden2b * iden2 * iden2;
+        bigb = denb;
+        bn2b -= denb;
+      }
+      mb += bigb * (Sv - t.sm);
+      Sbv += bigb * m;
+      sb.sm -= bigb * m;
+      mb += sb.rs[sd] * t.ism[sd];
+      ismb += sb.rs[sd] * m;
+      const double tism = -ismb * t.ism[sd] * t.ism[sd];
+      Sbv += tism;
+      sb.sm -= tism;
+      if (sd) {
+        drb += db_; mrb += mb; srb += Sbv; ptrb += ptb; urb[6] += enb;
+      } else {
+        dlb += db_; mlb += mb; slb += Sbv; ptlb += ptb; ulb[6] += enb;
+      }
+    }
+    bnb += 2.0 * bn * bn2b;
+    // contact speed and star total pressure
+    const double dw = wr[1] - wl[1];
+    const double nsm = t.mr * wr[1] - t.ml * wl[1] + t.ptl - t.ptr;
+    const double npt = t.ml * t.mr * dw + t.mr * t.ptl - t.ml * t.ptr;
+    const double nsmb = sb.sm * t.iden, nptb = ptsb * t.iden;
+    const double idenb = sb.sm * nsm + ptsb * npt;
+    mrb += nsmb * wr[1] + nptb * (t.ml * dw + t.ptl);
+    mlb += -nsmb * wl[1] + nptb * (t.mr * dw - t.ptr);
+    wrb[1] += nsmb * t.mr + nptb * t.ml * t.mr;
+    wlb[1] += -nsmb * t.ml - nptb * t.ml * t.mr;
+    ptlb += nsmb + nptb * t.mr;
+    ptrb += -nsmb - nptb * t.ml;
+    const double dden = -idenb * t.iden * t.iden;
+    mrb += dden;
+    mlb -= dden;
+    dlb += mlb * wl[0];
+    wlb[0] += mlb * t.dl;
+    drb += mrb * wr[0];
+    wrb[0] += mrb * t.dr;
+    slb += dlb;
+    wlb[1] -= dlb;
+    srb += drb;
+    wrb[1] -= drb;
+  }
+  // alpha+- = max(0, S_R), max(0, -S_L)
+  if (t.sr > 0.0) srb += apb;
+  if (-t.sl > 0.0) slb -= amb;
+  // S_L = min(u_L, u_R) - c, S_R = max(u_L, u_R) + c, c = max(c_L, c_R);
+  // the selected argument takes the cotangent (the first one on ties)
+  if (wr[1] < wl[1]) wrb[1] += slb; else wlb[1] += slb;
+  if (wr[1] > wl[1]) wrb[1] += srb; else wlb[1] += srb;
+  const double cmb = srb - slb;
+  if (t.cr > t.cl) cfast_vjp(g, wr, bn, cmb, wrb, bnb);
+  else cfast_vjp(g, wl, bn, cmb, wlb, bnb);
+  phys_vjp(igm1, wl, bn, ulb, flb, ptlb, wlb, bnb);
+  phys_vjp(igm1, wr, bn, urb, frb, ptrb, wrb, bnb);
 }
 
 // Edge-partial slots: d E / d input times Ebar.
@@ -237,27 +561,16 @@ __device__ __forceinline__ void face_adjoint(const double* __restrict__ U,
   constexpr int C2 = (D + 1) % 3;  // and a b-face of C2
   if (DIM == 3 || C1 == 2) edge_to_face<C1, 0, LIM>(U, FW, EB, g, i, j, k, c, apbar, ambar, v1bar, bbar);
   if (DIM == 3 || C2 == 2) edge_to_face<C2, 1, LIM>(U, FW, EB, g, i, j, k, c, apbar, ambar, v2bar, bbar);
-  // Riemann vector-Jacobian product, one dual pass per input
+  // Riemann vector-Jacobian product: one reverse sweep
   double wl[7], wr[7], bn;
   face_inputs<DIM, D, LIM>(U, g, i, j, k, wl, wr, bn);
   double* wb = bf.WB + (int64_t)D * 14 * n + c;
-  double bnbar = 0.0;
-#pragma unroll 1
-  for (int in = 0; in < 15; ++in) {
-    Dual dl[7], dr[7];
+  double wlb[7], wrb[7], bnbar;
+  riemann_vjp<RS>(g.gamma, wl, wr, bn, fb, apbar, ambar, v1bar, v2bar, wlb, wrb, bnbar);
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      dl[q] = Dual(wl[q], in == q ? 1.0 : 0.0);
-      dr[q] = Dual(wr[q], in == 7 + q ? 1.0 : 0.0);
-    }
-    const Dual dbn(bn, in == 14 ? 1.0 : 0.0);
-    RiemannOut<Dual> o;
-    riemann<RS, Dual>(Dual(g.gamma), dl, dr, dbn, o);
-    double acc = apbar * o.ap.d + ambar * o.am.d + v1bar * o.v1.d + v2bar * o.v2.d;
-#pragma unroll
-    for (int q = 0; q < 7; ++q) acc += fb[q] * o.f[q].d;
-    if (in < 14) wb[(int64_t)in * n] = acc;
-    else bnbar = acc;
+  for (int q = 0; q < 7; ++q) {
+    wb[(int64_t)q * n] = wlb[q];
+    wb[(int64_t)(7 + q) * n] = wrb[q];
   }
   bf.BF[(int64_t)D * n + c] = bnbar + bbar;
 }

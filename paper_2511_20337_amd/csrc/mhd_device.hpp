@@ -161,14 +161,35 @@ __device__ __forceinline__ void phys(R igm1, const R* w, R bn, R* u, R* f, R& pt
 template <class R> struct DegenerateTol { static constexpr double value = 1e-12; };
 template <> struct DegenerateTol<float> { static constexpr double value = 1e-12 * 536870912.0; };
 
+// Intermediate values of one Riemann solve, recorded for the hand-written
+// reverse sweep of the adjoint (RiemannTape) or not at all (NoTape, which the
+// forward kernels use; the compiler drops every store).
+struct NoTape {
+  static constexpr bool on = false;
+};
+struct RiemannTape {
+  static constexpr bool on = true;
+  // region: 0 F_L, 1 F_R (outside the fan), 2 HLL fan, 3 F*_L, 4 F**_L,
+  // 5 F**_R, 6 F*_R
+  int region;
+  double ul[7], fl[7], ur[7], fr[7], ptl, ptr, cl, cr, sl, sr, ap, am, isum, v1, v2;
+  double idn;                                     // HLL fan
+  double dl, dr, ml, mr, iden, sm, pts;           // HLLD contact
+  double ism[2], rs[2], big[2], den[2], iden2[2], fv[2], fb[2];
+  double vs[2], ws[2], b1s[2], b2s[2], vb[2], vbs[2], es[2];
+  bool deg[2];
+  double sql, sqr, abn, sls, srs, sgn, isq, ssq, vss, wss, b1ss, b2ss, vbss, ess;
+};
+
 // HLL (RS 1) or HLLD (RS 0) flux between face-frame states wl | wr with
 // continuous normal field bn. Wave-speed bounds: S_L = min(u_L,u_R) - c,
 // S_R = max(u_L,u_R) + c, c = max(c_f,L, c_f,R). HLLD: the four-state solver
 // of Miyoshi & Kusano (contact S_M, Alfven fronts S*_L, S*_R); when
 // rho (S-u)(S-S_M) - bn^2 vanishes (relative DegenerateTol) the tangential
 // fields of that side's star state are left unchanged. Region ties go left.
-template <int RS, class R>
-__device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, RiemannOut<R>& o) {
+template <int RS, class R, class T>
+__device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn,
+                                             RiemannOut<R>& o, T& tp) {
   R ul[7], fl[7], ur[7], fr[7], ptl, ptr;
   const R igm1 = rcp_r(g - R(1));  // 1/(gamma-1)
   phys(igm1, wl, bn, ul, fl, ptl);
@@ -180,20 +201,29 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
   const R sr = max_r(wl[1], wr[1]) + cm;
   o.ap = max_r(R(0), sr);
   o.am = max_r(R(0), -sl);
-  {
-    const R isum = rcp_r(o.ap + o.am);
-    o.v1 = fma_r(o.ap, wl[2], o.am * wr[2]) * isum;
-    o.v2 = fma_r(o.ap, wl[3], o.am * wr[3]) * isum;
+  const R isum = rcp_r(o.ap + o.am);
+  o.v1 = fma_r(o.ap, wl[2], o.am * wr[2]) * isum;
+  o.v2 = fma_r(o.ap, wl[3], o.am * wr[3]) * isum;
+  if constexpr (T::on) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      tp.ul[q] = ul[q]; tp.fl[q] = fl[q]; tp.ur[q] = ur[q]; tp.fr[q] = fr[q];
+    }
+    tp.ptl = ptl; tp.ptr = ptr; tp.cl = cl; tp.cr = cr; tp.sl = sl; tp.sr = sr;
+    tp.ap = o.ap; tp.am = o.am; tp.isum = isum; tp.v1 = o.v1; tp.v2 = o.v2;
   }
   if (RS == 1) {
     if (sl >= R(0)) {
+      if constexpr (T::on) tp.region = 0;
 #pragma unroll
       for (int q = 0; q < 7; ++q) o.f[q] = fl[q];
     } else if (sr <= R(0)) {
+      if constexpr (T::on) tp.region = 1;
 #pragma unroll
       for (int q = 0; q < 7; ++q) o.f[q] = fr[q];
     } else {
       const R idn = rcp_r(sr - sl);
+      if constexpr (T::on) { tp.region = 2; tp.idn = idn; }
 #pragma unroll
       for (int q = 0; q < 7; ++q)
         o.f[q] = fma_r(sl * sr, ur[q] - ul[q], fma_r(sr, fl[q], -sl * fr[q])) * idn;
@@ -201,11 +231,13 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
     return;
   }
   if (sl > R(0)) {
+    if constexpr (T::on) tp.region = 0;
 #pragma unroll
     for (int q = 0; q < 7; ++q) o.f[q] = fl[q];
     return;
   }
   if (sr < R(0)) {
+    if constexpr (T::on) tp.region = 1;
 #pragma unroll
     for (int q = 0; q < 7; ++q) o.f[q] = fr[q];
     return;
@@ -216,6 +248,9 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
   const R sm = fma_r(mr, wr[1], fma_r(-ml, wl[1], ptl - ptr)) * iden;
   const R pts = fma_r(ml * mr, wr[1] - wl[1], fma_r(mr, ptl, -ml * ptr)) * iden;
   const R bn2 = bn * bn;
+  if constexpr (T::on) {
+    tp.dl = dl; tp.dr = dr; tp.ml = ml; tp.mr = mr; tp.iden = iden; tp.sm = sm; tp.pts = pts;
+  }
 
   // star states, one side at a time: s = 0 left, 1 right
   R rs[2], vs[2], ws[2], b1s[2], b2s[2], es[2];
@@ -231,7 +266,8 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
     rs[s] = m * ism;
     const R big = m * (S - sm);
     const R den = big - bn2;
-    if (abs_r(den) <= R(DegenerateTol<R>::value) * (abs_r(big) + bn2)) {
+    const bool deg = abs_r(den) <= R(DegenerateTol<R>::value) * (abs_r(big) + bn2);
+    if (deg) {
       vs[s] = w[2]; ws[s] = w[3]; b1s[s] = w[4]; b2s[s] = w[5];
     } else {
       const R iden2 = rcp_r(den);
@@ -241,17 +277,25 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
       const R fb = fma_r(m, d, -bn2) * iden2;
       b1s[s] = w[4] * fb;
       b2s[s] = w[5] * fb;
+      if constexpr (T::on) { tp.iden2[s] = iden2; tp.fv[s] = fv; tp.fb[s] = fb; }
     }
     const R vb = fma_r(w[3], w[5], fma_r(w[2], w[4], w[1] * bn));
     const R vbs = fma_r(ws[s], b2s[s], fma_r(vs[s], b1s[s], sm * bn));
     es[s] = fma_r(bn, vb - vbs, fma_r(pts, sm, fma_r(d, en, -pt * w[1]))) * ism;
+    if constexpr (T::on) {
+      tp.ism[s] = ism; tp.rs[s] = rs[s]; tp.big[s] = big; tp.den[s] = den; tp.deg[s] = deg;
+      tp.vs[s] = vs[s]; tp.ws[s] = ws[s]; tp.b1s[s] = b1s[s]; tp.b2s[s] = b2s[s];
+      tp.vb[s] = vb; tp.vbs[s] = vbs; tp.es[s] = es[s];
+    }
   }
   const R sql = sqrt_r(rs[0]), sqr = sqrt_r(rs[1]);
   const R abn = abs_r(bn);
   const R sls = sm - div_r(abn, sql);
   const R srs = sm + div_r(abn, sqr);
+  if constexpr (T::on) { tp.sql = sql; tp.sqr = sqr; tp.abn = abn; tp.sls = sls; tp.srs = srs; }
 
   if (sls >= R(0)) {  // F*_L
+    if constexpr (T::on) tp.region = 3;
     const R us[7] = {rs[0], rs[0] * sm, rs[0] * vs[0], rs[0] * ws[0], b1s[0], b2s[0], es[0]};
 #pragma unroll
     for (int q = 0; q < 7; ++q) o.f[q] = fma_r(sl, us[q] - ul[q], fl[q]);
@@ -265,8 +309,13 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
   const R b1ss = fma_r(ssq, vs[1] - vs[0], fma_r(sql, b1s[1], sqr * b1s[0])) * isq;
   const R b2ss = fma_r(ssq, ws[1] - ws[0], fma_r(sql, b2s[1], sqr * b2s[0])) * isq;
   const R vbss = fma_r(vss, b1ss, wss * b2ss);
+  if constexpr (T::on) {
+    tp.sgn = sgn; tp.isq = isq; tp.ssq = ssq; tp.vss = vss; tp.wss = wss; tp.b1ss = b1ss;
+    tp.b2ss = b2ss; tp.vbss = vbss;
+  }
   if (sm >= R(0)) {  // F**_L
     const R ess = fma_r(-sgn * sql, fma_r(vs[0], b1s[0], ws[0] * b2s[0]) - vbss, es[0]);
+    if constexpr (T::on) { tp.region = 4; tp.ess = ess; }
     const R us[7] = {rs[0], rs[0] * sm, rs[0] * vs[0], rs[0] * ws[0], b1s[0], b2s[0], es[0]};
     const R uss[7] = {rs[0], rs[0] * sm, rs[0] * vss, rs[0] * wss, b1ss, b2ss, ess};
 #pragma unroll
@@ -279,6 +328,7 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
   const R us[7] = {rs[1], rs[1] * sm, rs[1] * vs[1], rs[1] * ws[1], b1s[1], b2s[1], es[1]};
   if (srs >= R(0)) {  // F**_R
     const R ess = fma_r(sgn * sqr, fma_r(vs[1], b1s[1], ws[1] * b2s[1]) - vbss, es[1]);
+    if constexpr (T::on) { tp.region = 5; tp.ess = ess; }
     const R uss[7] = {rs[1], rs[1] * sm, rs[1] * vss, rs[1] * wss, b1ss, b2ss, ess};
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
@@ -287,8 +337,15 @@ __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, Rie
     }
     return;
   }
+  if constexpr (T::on) tp.region = 6;
 #pragma unroll
   for (int q = 0; q < 7; ++q) o.f[q] = fma_r(sr, us[q] - ur[q], fr[q]);  // F*_R
+}
+
+template <int RS, class R>
+__device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, RiemannOut<R>& o) {
+  NoTape tp;
+  riemann_core<RS, R, NoTape>(g, wl, wr, bn, o, tp);
 }
 
 // Upwind edge EMF for component c with cyclic pair (a, b); the exact value

@@ -69,6 +69,49 @@ def test_adjoint_elementwise(dev, dim, lim, solver):
     assert dtbar == pytest.approx(float((ubar * jdt).sum()), rel=1e-11, abs=1e-14)
 
 
+def _special_state(case):
+    """Tie-free states that drive the Riemann solver into its other branches:
+    supersonic faces both ways (HLLD early outs), a zero normal field on the
+    z-faces (sign(0), no Alfven fan), and a fluid at rest (min/max of equal
+    normal velocities)."""
+    s, U = W.generic_state(3, 5, 4, 4, "vanleer", "hlld", seed=1)
+    V = O.prim(O.cfg_from(s), U)
+    bx, by, bz = U[5].copy(), U[6].copy(), U[7].copy()
+    if case == "supersonic_up":
+        V[1] += 2.5
+    elif case == "supersonic_down":
+        V[1] -= 2.5
+    elif case == "bz_zero":
+        bz = 0.0 * bz
+    elif case == "at_rest":
+        V[1:4] = 0.0
+    return s, W.assemble(s, V[0], V[1], V[2], V[3], V[4], bx, by, bz)
+
+
+@pytest.mark.parametrize("case", ["supersonic_up", "supersonic_down", "bz_zero", "at_rest"])
+@pytest.mark.parametrize("solver", ["hlld", "hll"])
+def test_adjoint_elementwise_special_states(dev, case, solver):
+    s, U = _special_state(case)
+    s = dict(s, riemann=solver)
+    c = O.cfg_from(s)
+    dt = O.dt(c, U)
+    rng = np.random.default_rng(7)
+    ubar = rng.normal(size=U.shape)
+    got, dtbar = gpu_adjoint(s, U, dt, ubar, dev)
+    ref = np.zeros(U.size)
+    e = np.zeros(U.size)
+    for idx in range(U.size):
+        e[idx] = 1.0
+        _, jv = O.step_jvp(c, U, e.reshape(U.shape), dt)
+        ref[idx] = float((ubar * jv).sum())
+        e[idx] = 0.0
+    ref = ref.reshape(U.shape)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-11 * scale, (case, np.abs(got - ref).max() / scale)
+    _, jdt = O.step_jvp(c, U, np.zeros_like(U), dt, 1.0)
+    assert dtbar == pytest.approx(float((ubar * jdt).sum()), rel=1e-11, abs=1e-14)
+
+
 @pytest.mark.parametrize("case", ["2d_32", "3d_12", "3d_16_minmod_hll"])
 def test_adjoint_dot_product(dev, case):
     if case == "2d_32":
