@@ -165,6 +165,27 @@ def copy_probe(mib: int) -> int:
     return 0
 
 
+def only_part(part, n, steps, warmup):
+    """One extra measurement alone, printed as one JSON line."""
+    from paper_2511_20337_amd import workloads as W
+    if part == "mixed":
+        sm, Um = W.turbulence_3d_lowbeta(n)
+        el, kt, _, phys = time_gpu(sm, Um, steps, warmup)
+        out = {"part": part, "value": n ** 3 * steps / el / 1e6, "unit": "Mcell-updates/s",
+               "workload": "turbulence_3d_lowbeta_%d" % n, "physical": phys,
+               "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]}}
+    elif part == "adjoint":
+        adj, fwd = time_adjoint(512, 64, 8)
+        out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
+               "workload": "kelvin_helmholtz_2d_512"}
+    else:
+        adj, fwd = time_adjoint_blast(256, 16, 4)
+        out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
+               "workload": "blast_3d_256_fp64"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,9 +200,13 @@ def main(argv=None):
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters) and exit")
+    ap.add_argument("--only", choices=("mixed", "adjoint", "adjoint_3d"), default=None,
+                    help="run only this extra measurement and print it (for profiling)")
     args = ap.parse_args(argv)
     if args.copy_probe:
         return copy_probe(args.copy_probe)
+    if args.only:
+        return only_part(args.only, args.n, args.steps, args.warmup)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
