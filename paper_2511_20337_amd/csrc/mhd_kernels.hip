@@ -42,6 +42,19 @@ struct RowTile {
   static constexpr int NT = TX * TY;  // workgroup size
 };
 
+// Face records (fluxes, alpha+-, HLL-weighted velocities) are stored in the
+// precision the solver computed them in: FP64, or FP32 in the mixed mode
+// (exact, and half the bytes for the EMF and update kernels). The workspace
+// holds dim * NSLOT * n doubles either way.
+template <class R>
+__device__ __forceinline__ R* face_records(double* FW) {
+  return reinterpret_cast<R*>(FW);
+}
+template <class R>
+__device__ __forceinline__ const R* face_records(const double* FW) {
+  return reinterpret_cast<const R*>(FW);
+}
+
 struct MarchGrid {
   int ntx, nty, nzc, lz;  // column tiles in x, y; runs of lz planes along z
   unsigned nblocks;
@@ -115,23 +128,23 @@ __device__ __forceinline__ double emf_comp(const double* __restrict__ U,
                                            int j, int k, int64_t c) {
   constexpr int A = (C + 1) % 3, B = (C + 2) % 3;
   const int64_t n = g.n;
-  const double* fa = FW + (int64_t)A * NSLOT * n;  // a-faces (normal A)
-  const double* fb = FW + (int64_t)B * NSLOT * n;  // b-faces (normal B)
+  const R* fa = face_records<R>(FW) + (int64_t)A * NSLOT * n;  // a-faces (normal A)
+  const R* fb = face_records<R>(FW) + (int64_t)B * NSLOT * n;  // b-faces (normal B)
   const int64_t cmb = shifted<B>(g, i, j, k, -1);  // a-face below the edge along B
   const int64_t cma = shifted<A>(g, i, j, k, -1);  // b-face below the edge along A
   const int64_t a2 = shifted<A>(g, i, j, k, -2), a1 = shifted<A>(g, i, j, k, 1);
   const int64_t b2 = shifted<B>(g, i, j, k, -2), b1 = shifted<B>(g, i, j, k, 1);
-  const double* vbA = fb + S_V2 * n;  // on b-faces, v_A (slot V2 of the B frame)
+  const R* vbA = fb + S_V2 * n;  // on b-faces, v_A (slot V2 of the B frame)
   const double* bBf = U + (F_BX + B) * n;
-  const double* vaB = fa + S_V1 * n;  // on a-faces, v_B (slot V1 of the A frame)
+  const R* vaB = fa + S_V1 * n;  // on a-faces, v_B (slot V1 of the A frame)
   const double* bAf = U + (F_BX + A) * n;
-  const R wv[4] = {(R)vbA[a2], (R)vbA[cma], (R)vbA[c], (R)vbA[a1]};
+  const R wv[4] = {vbA[a2], vbA[cma], vbA[c], vbA[a1]};
   const R wb[4] = {(R)bBf[a2], (R)bBf[cma], (R)bBf[c], (R)bBf[a1]};
-  const R sv[4] = {(R)vaB[b2], (R)vaB[cmb], (R)vaB[c], (R)vaB[b1]};
+  const R sv[4] = {vaB[b2], vaB[cmb], vaB[c], vaB[b1]};
   const R sb[4] = {(R)bAf[b2], (R)bAf[cmb], (R)bAf[c], (R)bAf[b1]};
-  return emf_core<LIM, R>((R)fa[S_AP * n + cmb], (R)fa[S_AP * n + c], (R)fa[S_AM * n + cmb],
-                          (R)fa[S_AM * n + c], (R)fb[S_AP * n + cma], (R)fb[S_AP * n + c],
-                          (R)fb[S_AM * n + cma], (R)fb[S_AM * n + c], wv, wb, sv, sb);
+  return emf_core<LIM, R>(fa[S_AP * n + cmb], fa[S_AP * n + c], fa[S_AM * n + cmb],
+                          fa[S_AM * n + c], fb[S_AP * n + cma], fb[S_AP * n + c],
+                          fb[S_AM * n + cma], fb[S_AM * n + c], wv, wb, sv, sb);
 }
 
 // 3D EMF kernel marching along z over 64 x 4 columns: the inputs of E_x and
@@ -159,9 +172,9 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
   const int k0 = zc * mg.lz;
   const int k1 = min(k0 + mg.lz, g.nz);
   const int64_t n = g.n;
-  const double* fx = FW;
-  const double* fy = FW + (int64_t)NSLOT * n;
-  const double* fz = FW + (int64_t)2 * NSLOT * n;
+  const R* fx = face_records<R>(FW);
+  const R* fy = fx + (int64_t)NSLOT * n;
+  const R* fz = fx + (int64_t)2 * NSLOT * n;
   const double* bx = U + F_BX * n;
   const double* by = U + F_BY * n;
   const double* bz = U + F_BZ * n;
@@ -171,17 +184,17 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int64_t cs = lin(g, i, j, wrap_any(k0 - 2 + s, g.nz));
-    yv[s] = (R)fy[S_V1 * n + cs];
+    yv[s] = fy[S_V1 * n + cs];
     yb[s] = (R)by[cs];
-    xv[s] = (R)fx[S_V2 * n + cs];
+    xv[s] = fx[S_V2 * n + cs];
     xb[s] = (R)bx[cs];
   }
   {
     const int64_t cm = lin(g, i, j, wrap_any(k0 - 1, g.nz));
-    yap[0] = (R)fy[S_AP * n + cm];
-    yam[0] = (R)fy[S_AM * n + cm];
-    xap[0] = (R)fx[S_AP * n + cm];
-    xam[0] = (R)fx[S_AM * n + cm];
+    yap[0] = fy[S_AP * n + cm];
+    yam[0] = fy[S_AM * n + cm];
+    xap[0] = fx[S_AP * n + cm];
+    xam[0] = fx[S_AM * n + cm];
   }
   const int im2 = wrap(i - 2, g.nx), im1 = wrap(i - 1, g.nx), ip1 = wrap(i + 1, g.nx);
   const int jm2 = wrap(j - 2, g.ny), jm1 = wrap(j - 1, g.ny), jp1 = wrap(j + 1, g.ny);
@@ -190,42 +203,44 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
     const int64_t cp = lin(g, i, j, wrap(k + 1, g.nz));
     const int64_t cjm2 = lin(g, i, jm2, k), cjm1 = lin(g, i, jm1, k), cjp1 = lin(g, i, jp1, k);
     const int64_t cim2 = lin(g, im2, j, k), cim1 = lin(g, im1, j, k), cip1 = lin(g, ip1, j, k);
-    // all FP64 loads of this plane first, then the conversions to R (keeps
-    // the loads in flight together when R is float)
-    const double* vz2 = fz + S_V2 * n;
-    const double* vz1 = fz + S_V1 * n;
-    double d[24];
-    d[0] = fy[S_V1 * n + cp]; d[1] = by[cp]; d[2] = fx[S_V2 * n + cp]; d[3] = bx[cp];
-    d[4] = fy[S_AP * n + c]; d[5] = fy[S_AM * n + c]; d[6] = fx[S_AP * n + c];
-    d[7] = fx[S_AM * n + c];
-    d[8] = vz2[cjm2]; d[9] = vz2[cjm1]; d[10] = vz2[c]; d[11] = vz2[cjp1];
-    d[12] = bz[cjm2]; d[13] = bz[cjm1]; d[14] = bz[c]; d[15] = bz[cjp1];
-    d[16] = vz1[cim2]; d[17] = vz1[cim1]; d[18] = vz1[c]; d[19] = vz1[cip1];
-    d[20] = bz[cim2]; d[21] = bz[cim1]; d[22] = bz[cip1];
-    d[23] = fz[S_AP * n + cjm1];
-    const double zapc = fz[S_AP * n + c], zamj = fz[S_AM * n + cjm1], zamc = fz[S_AM * n + c];
-    const double zapi = fz[S_AP * n + cim1], zami = fz[S_AM * n + cim1];
-    yv[3] = (R)d[0];
-    yb[3] = (R)d[1];
-    xv[3] = (R)d[2];
-    xb[3] = (R)d[3];
-    yap[1] = (R)d[4];
-    yam[1] = (R)d[5];
-    xap[1] = (R)d[6];
-    xam[1] = (R)d[7];
+    // all loads of this plane first (face records in R, staggered fields in
+    // FP64), then the conversions to R: the loads stay in flight together
+    const R* vz2 = fz + S_V2 * n;
+    const R* vz1 = fz + S_V1 * n;
+    R r[15];
+    double d[9];
+    r[0] = fy[S_V1 * n + cp]; r[1] = fx[S_V2 * n + cp];
+    r[2] = fy[S_AP * n + c]; r[3] = fy[S_AM * n + c]; r[4] = fx[S_AP * n + c];
+    r[5] = fx[S_AM * n + c];
+    r[6] = vz2[cjm2]; r[7] = vz2[cjm1]; r[8] = vz2[c]; r[9] = vz2[cjp1];
+    r[10] = vz1[cim2]; r[11] = vz1[cim1]; r[12] = vz1[c]; r[13] = vz1[cip1];
+    r[14] = fz[S_AP * n + cjm1];
+    const R zapc = fz[S_AP * n + c], zamj = fz[S_AM * n + cjm1], zamc = fz[S_AM * n + c];
+    const R zapi = fz[S_AP * n + cim1], zami = fz[S_AM * n + cim1];
+    d[0] = by[cp]; d[1] = bx[cp];
+    d[2] = bz[cjm2]; d[3] = bz[cjm1]; d[4] = bz[c]; d[5] = bz[cjp1];
+    d[6] = bz[cim2]; d[7] = bz[cim1]; d[8] = bz[cip1];
+    yv[3] = r[0];
+    yb[3] = (R)d[0];
+    xv[3] = r[1];
+    xb[3] = (R)d[1];
+    yap[1] = r[2];
+    yam[1] = r[3];
+    xap[1] = r[4];
+    xam[1] = r[5];
     // E_x: (A, B) = (y, z); a-faces are y-faces, b-faces z-faces
     {
-      const R wv[4] = {(R)d[8], (R)d[9], (R)d[10], (R)d[11]};
-      const R wb[4] = {(R)d[12], (R)d[13], (R)d[14], (R)d[15]};
-      EW[c] = emf_core<LIM, R>(yap[0], yap[1], yam[0], yam[1], (R)d[23], (R)zapc, (R)zamj,
-                               (R)zamc, wv, wb, yv, yb);
+      const R wv[4] = {r[6], r[7], r[8], r[9]};
+      const R wb[4] = {(R)d[2], (R)d[3], (R)d[4], (R)d[5]};
+      EW[c] = emf_core<LIM, R>(yap[0], yap[1], yam[0], yam[1], r[14], zapc, zamj, zamc, wv, wb,
+                               yv, yb);
     }
     // E_y: (A, B) = (z, x); a-faces are z-faces, b-faces x-faces
     {
-      const R sv[4] = {(R)d[16], (R)d[17], (R)d[18], (R)d[19]};
-      const R sb[4] = {(R)d[20], (R)d[21], (R)d[14], (R)d[22]};
-      EW[n + c] = emf_core<LIM, R>((R)zapi, (R)zapc, (R)zami, (R)zamc, xap[0], xap[1], xam[0],
-                                   xam[1], xv, xb, sv, sb);
+      const R sv[4] = {r[10], r[11], r[12], r[13]};
+      const R sb[4] = {(R)d[6], (R)d[7], (R)d[4], (R)d[8]};
+      EW[n + c] = emf_core<LIM, R>(zapi, zapc, zami, zamc, xap[0], xap[1], xam[0], xam[1], xv, xb,
+                                   sv, sb);
     }
     EW[2 * n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
 #pragma unroll
@@ -257,7 +272,8 @@ __global__ __launch_bounds__(RowTile::NT) void k_emf(const double* __restrict__ 
 }
 
 // STAGE 0: out = L(U); 1: out = U + dt L(U); 2: out = (U0 + (U + dt L(U))) / 2.
-template <int DIM, int STAGE>
+// R: the precision of the stored fluxes (differenced in FP64).
+template <int DIM, int STAGE, class R>
 __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict__ U,
                                                    const double* U0, double* out,
                                                    const double* __restrict__ FW,
@@ -273,16 +289,17 @@ __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict
   const int64_t yp = lin(g, i, wrap(j + 1, g.ny), k);
   const int64_t zp = (DIM == 3) ? lin(g, i, j, wrap(k + 1, g.nz)) : c;
   const double idx = 1.0 / g.dx, idy = 1.0 / g.dy, idz = 1.0 / g.dz;
-  const double* fx = FW;
-  const double* fy = FW + (int64_t)NSLOT * n;
-  const double* fz = FW + (int64_t)2 * NSLOT * n;
+  const R* fx = face_records<R>(FW);
+  const R* fy = fx + (int64_t)NSLOT * n;
+  const R* fz = fx + (int64_t)2 * NSLOT * n;
   double L[8];
   constexpr int ncell = (DIM == 3) ? 5 : 6;
 #pragma unroll
   for (int qq = 0; qq < ncell; ++qq) {
     const int q = qq;  // slot == field for rho..E; slot S_BZ for the 2D B_z
-    double acc = (fx[q * n + xp] - fx[q * n + c]) * idx + (fy[q * n + yp] - fy[q * n + c]) * idy;
-    if (DIM == 3) acc += (fz[q * n + zp] - fz[q * n + c]) * idz;
+    double acc = ((double)fx[q * n + xp] - (double)fx[q * n + c]) * idx +
+                 ((double)fy[q * n + yp] - (double)fy[q * n + c]) * idy;
+    if (DIM == 3) acc += ((double)fz[q * n + zp] - (double)fz[q * n + c]) * idz;
     L[qq == 5 ? 7 : qq] = -acc;
   }
   if (DIM == 3) {
@@ -376,17 +393,17 @@ __device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM],
   RiemannOut<R> o;
   riemann<RS, R>((R)g.gamma, wl, wr, bn, o);
   const int64_t n = g.n;
-  double* fw = FW + (int64_t)D * NSLOT * n + c;
-  fw[S_RHO * n] = (double)o.f[0];
-  fw[(S_MX + D) * n] = (double)o.f[1];
-  fw[(S_MX + T1) * n] = (double)o.f[2];
-  fw[(S_MX + T2) * n] = (double)o.f[3];
-  fw[S_EN * n] = (double)o.f[6];
-  if (DIM == 2) fw[S_BZ * n] = (double)((D == 0) ? o.f[5] : o.f[4]);  // B_z is t2 of x, t1 of y
-  fw[S_AP * n] = (double)o.ap;
-  fw[S_AM * n] = (double)o.am;
-  fw[S_V1 * n] = (double)o.v1;
-  fw[S_V2 * n] = (double)o.v2;
+  R* fw = face_records<R>(FW) + (int64_t)D * NSLOT * n + c;
+  fw[S_RHO * n] = o.f[0];
+  fw[(S_MX + D) * n] = o.f[1];
+  fw[(S_MX + T1) * n] = o.f[2];
+  fw[(S_MX + T2) * n] = o.f[3];
+  fw[S_EN * n] = o.f[6];
+  if (DIM == 2) fw[S_BZ * n] = (D == 0) ? o.f[5] : o.f[4];  // B_z is t2 of x, t1 of y
+  fw[S_AP * n] = o.ap;
+  fw[S_AM * n] = o.am;
+  fw[S_V1 * n] = o.v1;
+  fw[S_V2 * n] = o.v2;
 }
 
 // Face kernel: primitives of the tile and its cross halo are recovered once
@@ -523,16 +540,16 @@ __device__ __forceinline__ void march_solve(const R* wl, const R* wr, R bn,
   RiemannOut<R> o;
   riemann<RS, R>((R)g.gamma, wl, wr, bn, o);
   const int64_t n = g.n;
-  double* fw = FW + (int64_t)D * NSLOT * n + c;
-  fw[S_RHO * n] = (double)o.f[0];
-  fw[(S_MX + D) * n] = (double)o.f[1];
-  fw[(S_MX + T1) * n] = (double)o.f[2];
-  fw[(S_MX + T2) * n] = (double)o.f[3];
-  fw[S_EN * n] = (double)o.f[6];
-  fw[S_AP * n] = (double)o.ap;
-  fw[S_AM * n] = (double)o.am;
-  fw[S_V1 * n] = (double)o.v1;
-  fw[S_V2 * n] = (double)o.v2;
+  R* fw = face_records<R>(FW) + (int64_t)D * NSLOT * n + c;
+  fw[S_RHO * n] = o.f[0];
+  fw[(S_MX + D) * n] = o.f[1];
+  fw[(S_MX + T1) * n] = o.f[2];
+  fw[(S_MX + T2) * n] = o.f[3];
+  fw[S_EN * n] = o.f[6];
+  fw[S_AP * n] = o.ap;
+  fw[S_AM * n] = o.am;
+  fw[S_V1 * n] = o.v1;
+  fw[S_V2 * n] = o.v2;
 }
 
 // Lower x (D = 0) or y (D = 1) face of a cell of plane k: PLM over the four
@@ -779,17 +796,17 @@ hipError_t stage_impl(const StageArgs& a) {
       break;
     case 0:
       MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 0>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                hipLaunchKernelGGL((k_update<DIM, 0, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                    a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
       break;
     case 1:
       MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 1>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                hipLaunchKernelGGL((k_update<DIM, 1, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                    a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
       break;
     default:
       MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 2>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                hipLaunchKernelGGL((k_update<DIM, 2, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                    a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
       break;
   }
