@@ -53,7 +53,8 @@ KERNEL_TRAFFIC = {"faces": 202.0 + 216.0}
 
 
 def time_gpu(setup, U0, steps, warmup, timing=True):
-    """Time `steps` whole steps (device dt + RK2 step) after `warmup` steps.
+    """Time `steps` whole steps (CFL dt on the device + RK2 step, one
+    mhd_step_cfl call each) after `warmup` steps.
     Returns (seconds, per-kernel event totals, final state, physical?)."""
     import torch
     from paper_2511_20337_amd import mhd
@@ -61,15 +62,13 @@ def time_gpu(setup, U0, steps, warmup, timing=True):
     ctx = mhd.Context(setup, dev)
     U = torch.from_numpy(U0).to(dev)
     for _ in range(warmup):
-        ctx.dt_device(U)
-        ctx.step_device_dt(U)
+        ctx.step_cfl(U)
     torch.cuda.synchronize()
     if timing:
         mhd.mhd_timing(ctx.ctx, True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.dt_device(U)
-        ctx.step_device_dt(U)
+        ctx.step_cfl(U)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt = mhd.mhd_timing_read(ctx.ctx) if timing else {}

@@ -2,6 +2,7 @@
 // workspace layout and the launch sequence of each call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -152,8 +153,10 @@ mhd::StageArgs stage_args(mhd_ctx* ctx, void* ws, hipStream_t s) {
   return a;
 }
 
+// One RK2 step. dt_cfl (3D only): dt is the CFL step of U, reduced by the
+// stage-1 face kernel and written to dt_cfl, which is also dtp.
 mhd_status run_step(mhd_ctx* ctx, double* U, double dt, const double* dtp, void* ws,
-                    hipStream_t s) {
+                    hipStream_t s, double* dt_cfl = nullptr) {
   double* U1 = reinterpret_cast<double*>(base(ws) + ctx->off_u1);
   mhd::StageArgs a = stage_args(ctx, ws, s);
   a.dt = dt;
@@ -162,8 +165,14 @@ mhd_status run_step(mhd_ctx* ctx, double* U, double dt, const double* dtp, void*
   a.U = U;
   a.U0 = nullptr;
   a.out = U1;
+  if (dt_cfl) {
+    a.cfl_partial = reinterpret_cast<double*>(base(ws) + ctx->off_partial);
+    a.cfl = ctx->cfg.cfl;
+    a.dt_out = dt_cfl;
+  }
   hipError_t e = mhd::launch_stage(a);
   if (e != hipSuccess) return device_fail(ctx, e, "stage 1");
+  a.cfl_partial = nullptr;
   a.stage = 2;
   a.U = U1;
   a.U0 = U;
@@ -225,9 +234,12 @@ mhd_status mhd_init(const mhd_config* cfg, mhd_ctx** out) {
   c->g.gamma = cfg->gamma;
   const size_t n = (size_t)c->g.n;
   c->cfl_blocks = kCflBlocks;
+  // CFL partials: of k_cfl, or (3D) one per face workgroup of the fused step
+  size_t npart = kCflBlocks;
+  if (cfg->dim == 3) npart = std::max(npart, mhd::stage_cfl_blocks(c->g));
   size_t off = kCtl;
   c->off_partial = off;
-  off = align_up(off + sizeof(double) * kCflBlocks);
+  off = align_up(off + sizeof(double) * npart);
   c->off_u1 = off;
   off = align_up(off + sizeof(double) * 8 * n);
   c->off_fw = off;
@@ -290,6 +302,18 @@ mhd_status mhd_step_device_dt(mhd_ctx* ctx, double* U, const double* dt_dev, voi
   if (!U || !dt_dev) return MHD_ERR_INVALID;
   if (!ws_ok(ctx, ws, ws_bytes, false)) return MHD_ERR_WORKSPACE;
   return run_step(ctx, U, 0.0, dt_dev, ws, static_cast<hipStream_t>(stream));
+}
+
+mhd_status mhd_step_cfl(mhd_ctx* ctx, double* U, double* dt_dev, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (!ctx) return MHD_ERR_INVALID;
+  if (!U || !dt_dev) return MHD_ERR_INVALID;
+  if (!ws_ok(ctx, ws, ws_bytes, false)) return MHD_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->cfg.dim == 3) return run_step(ctx, U, 0.0, dt_dev, ws, s, dt_dev);
+  mhd_status st = cfl_to(ctx, U, ws, dt_dev, s);  // 2D: the separate CFL pass
+  if (st != MHD_OK) return st;
+  return run_step(ctx, U, 0.0, dt_dev, ws, s);
 }
 
 mhd_status mhd_rhs(mhd_ctx* ctx, const double* U, double* L, void* ws, size_t ws_bytes,

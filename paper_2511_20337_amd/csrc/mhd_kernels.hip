@@ -504,6 +504,20 @@ __device__ __forceinline__ bool march_prim(const double* __restrict__ U, const G
   return ok;
 }
 
+// CFL bound of one cell from its FP64 primitives: min over directions of
+// dx_d / (|v_d| + c_f,d), the expression of k_cfl.
+__device__ __forceinline__ double cfl_bound(const Geom& g, const double* W, double m) {
+  const double dd[3] = {g.dx, g.dy, g.dz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double cf = cfast<double>(g.gamma, W[0], W[4], W[5 + d], W[5 + (d + 1) % 3],
+                                    W[5 + (d + 2) % 3]);
+    const double t = dd[d] / (__builtin_fabs(W[1 + d]) + cf);
+    m = (t < m) ? t : m;
+  }
+  return m;
+}
+
 // Store a core cell's primitives: slots 0..6 in ring plane rp, B_z in bz
 // plane bp (bp < 0: B_z not kept).
 template <class R>
@@ -573,10 +587,13 @@ __device__ __forceinline__ void march_face_xy(const R* lds, const int* o, const 
   march_solve<D, RS, R>(wl, wr, bn, FW, g, c);
 }
 
+// cflp != nullptr: also the CFL bound of the state, reduced over the cells
+// of this workgroup's column and run (each cell is the own cell of exactly
+// one workgroup and plane) into cflp[blockIdx.x]; k_cfl_final finishes it.
 template <int LIM, int RS, class R>
 __global__ __launch_bounds__(kBlock)
 void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g, MarchGrid mg,
-                   int* __restrict__ flag) {
+                   int* __restrict__ flag, double* __restrict__ cflp) {
   // slots of the z-face frame (rho, v_z, v_x, v_y, B_x, B_y, p): all in the ring
   constexpr int zslot[7] = {0, 3, 1, 2, 5, 6, 4};
   __shared__ MarchLds<R> L;
@@ -601,12 +618,22 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
   // prologue: own cells of planes k0-2 .. k0+1; ring gets k0-1 .. k0+1,
   // B_z of k0 and k0+1, halo of plane k0; the left state of the first z-face.
   R zl[7];
+  double cmin = __builtin_inf();  // CFL bound over this thread's own cells
   {
     R Vm2[8], Vm1[8], V0[8], Vp1[8];
     bad |= !march_prim<R>(U, g, i, j, k0 - 2, Vm2);
     bad |= !march_prim<R>(U, g, i, j, k0 - 1, Vm1);
-    bad |= !march_prim<R>(U, g, i, j, k0, V0);
-    bad |= !march_prim<R>(U, g, i, j, k0 + 1, Vp1);
+    {
+      double W[8];
+      bad |= !prim_at<3>(U, g, wrap_any(i, g.nx), wrap_any(j, g.ny), wrap_any(k0, g.nz), W);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) V0[q] = (R)W[q];
+      if (cflp && inside) cmin = cfl_bound(g, W, cmin);
+      bad |= !prim_at<3>(U, g, wrap_any(i, g.nx), wrap_any(j, g.ny), wrap_any(k0 + 1, g.nz), W);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Vp1[q] = (R)W[q];
+      if (cflp && inside && k0 + 1 < k1) cmin = cfl_bound(g, W, cmin);
+    }
     march_put_core<R>(lds, 0, -1, cidx, Vm1);  // k0-1: ring 0 (its B_z is not needed)
     march_put_core<R>(lds, 1, 1, cidx, V0);    // k0: ring 1, bz (k0 - kbase) & 1 = 1
     march_put_core<R>(lds, 2, 0, cidx, Vp1);   // k0+1: ring 2, bz 0
@@ -669,6 +696,7 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
       __syncthreads();  // plane k-1, B_z of plane k and the halo of plane k are free
       double W[8];
       bad |= !prim_from_raw<3>(nxt, g.gamma, W);
+      if (cflp && inside && k + 2 < k1) cmin = cfl_bound(g, W, cmin);
       R V[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) V[q] = (R)W[q];
@@ -680,6 +708,23 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
         for (int q = 0; q < 8; ++q) lds[kHaloOff + q * March::NHALO + threadIdx.x] = H[q];
       }
       __syncthreads();
+    }
+  }
+  if (cflp) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(cmin, off, 64);
+      cmin = (o < cmin) ? o : cmin;
+    }
+    __shared__ double red[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = cmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r = red[0];
+#pragma unroll
+      for (int w = 1; w < kBlock / 64; ++w) r = (red[w] < r) ? red[w] : r;
+      cflp[blockIdx.x] = r;
     }
   }
   if (bad) atomicOr(flag, 1);
@@ -756,20 +801,29 @@ TileGrid tile_grid(const Geom& g) {
   return tg;
 }
 
+MarchGrid march_grid(const Geom& g) {
+  MarchGrid mg;
+  mg.ntx = (g.nx + March::TX - 1) / March::TX;
+  mg.nty = (g.ny + March::TY - 1) / March::TY;
+  mg.lz = g.nz < kMarchRun ? g.nz : kMarchRun;
+  mg.nzc = (g.nz + mg.lz - 1) / mg.lz;
+  mg.nblocks = (unsigned)mg.ntx * (unsigned)mg.nty * (unsigned)mg.nzc;
+  return mg;
+}
+
 template <int DIM, int LIM, int RS, class R>
 hipError_t stage_impl(const StageArgs& a) {
   const TileGrid rg = tile_grid<RowTile>(a.g);
   const unsigned nb = rg.ntiles;
   if constexpr (DIM == 3) {
-    MarchGrid mg;
-    mg.ntx = (a.g.nx + March::TX - 1) / March::TX;
-    mg.nty = (a.g.ny + March::TY - 1) / March::TY;
-    mg.lz = a.g.nz < kMarchRun ? a.g.nz : kMarchRun;
-    mg.nzc = (a.g.nz + mg.lz - 1) / mg.lz;
-    mg.nblocks = (unsigned)mg.ntx * (unsigned)mg.nty * (unsigned)mg.nzc;
+    const MarchGrid mg = march_grid(a.g);
     MHD_TIMED(a, K_FACES,
               hipLaunchKernelGGL((k_faces_march<LIM, RS, R>), dim3(mg.nblocks), dim3(kBlock), 0,
-                                 a.stream, a.U, a.FW, a.g, mg, a.flag));
+                                 a.stream, a.U, a.FW, a.g, mg, a.flag, a.cfl_partial));
+    if (a.cfl_partial)  // dt of the state U, before the update kernels read it
+      MHD_TIMED(a, K_CFL_FINAL,
+                hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, a.cfl_partial,
+                                   (int)mg.nblocks, a.cfl, a.dt_out));
   } else {
     const TileGrid tg = tile_grid<Tile<DIM>>(a.g);
     MHD_TIMED(a, K_FACES,
@@ -827,6 +881,8 @@ hipError_t stage_lim(const StageArgs& a) {
 }
 
 }  // namespace
+
+size_t stage_cfl_blocks(const Geom& g) { return march_grid(g).nblocks; }
 
 hipError_t launch_stage(const StageArgs& a) {
   return (a.dim == 3) ? stage_lim<3>(a) : stage_lim<2>(a);

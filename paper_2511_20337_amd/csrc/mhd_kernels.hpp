@@ -33,6 +33,12 @@ struct StageArgs {
   int* flag;              // sticky unphysical flag
   hipStream_t stream;
   Timer* timer;           // nullable
+  // 3D stage 1 only, optional: the face kernel also reduces the CFL bound of U
+  // into cfl_partial (stage_cfl_blocks(g) doubles), and *dt_out = cfl * min
+  // is written before the update reads dtp (which then must be dt_out)
+  double* cfl_partial;
+  double cfl;
+  double* dt_out;
 };
 
 struct CflArgs {
@@ -56,6 +62,8 @@ struct CflArgs {
   } while (0)
 
 hipError_t launch_stage(const StageArgs& a);
+// number of CFL partials the 3D face kernel writes (one per workgroup)
+size_t stage_cfl_blocks(const Geom& g);
 hipError_t launch_cfl(const CflArgs& a);
 
 }  // namespace mhd

@@ -29,7 +29,7 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 
 # Every symbol include/mhd.h declares.
 SYMBOLS = ("mhd_init", "mhd_destroy", "mhd_workspace_bytes", "mhd_dt", "mhd_dt_device",
-           "mhd_step", "mhd_step_device_dt", "mhd_rhs", "mhd_adjoint_step",
+           "mhd_step", "mhd_step_device_dt", "mhd_step_cfl", "mhd_rhs", "mhd_adjoint_step",
            "mhd_adjoint_step_device", "mhd_check",
            "mhd_timing", "mhd_timing_read", "mhd_strerror", "mhd_last_error")
 
@@ -77,6 +77,7 @@ def lib():
             "mhd_dt_device": ([vp, vp, vp, sz, vp, vp], st),
             "mhd_step": ([vp, vp, ctypes.c_double, vp, sz, vp], st),
             "mhd_step_device_dt": ([vp, vp, vp, vp, sz, vp], st),
+            "mhd_step_cfl": ([vp, vp, vp, vp, sz, vp], st),
             "mhd_rhs": ([vp, vp, vp, vp, sz, vp], st),
             "mhd_adjoint_step": ([vp, vp, ctypes.c_double, vp, vp, dp, vp, sz, vp], st),
             "mhd_adjoint_step_device": ([vp, vp, ctypes.c_double, vp, vp, vp, vp, sz, vp], st),
@@ -166,6 +167,12 @@ def mhd_step_device_dt(ctx, U, dt_dev, ws) -> None:
     rc = lib().mhd_step_device_dt(ctx, U.data_ptr(), dt_dev.data_ptr(), ws.data_ptr(),
                                   ws.numel(), _stream(U.device))
     _raise(ctx, rc, "mhd_step_device_dt")
+
+
+def mhd_step_cfl(ctx, U, dt_dev, ws) -> None:
+    rc = lib().mhd_step_cfl(ctx, U.data_ptr(), dt_dev.data_ptr(), ws.data_ptr(), ws.numel(),
+                            _stream(U.device))
+    _raise(ctx, rc, "mhd_step_cfl")
 
 
 def mhd_rhs(ctx, U, L, ws) -> None:
@@ -267,6 +274,16 @@ class Context:
                            self.ws)
         return U
 
+    def step_cfl(self, U, dt_dev=None):
+        """One step with dt = the CFL step of U, left in dt_dev (default:
+        self.dt_dev); no host synchronisation."""
+        import torch
+        dt_dev = self.dt_dev if dt_dev is None else dt_dev
+        if dt_dev.dtype != torch.float64 or dt_dev.device != self.device or dt_dev.numel() < 1:
+            raise MHDError(MHD_ERR_INVALID, "dt_dev: a float64 tensor on the device")
+        mhd_step_cfl(self.ctx, self._state(U), dt_dev, self.ws)
+        return U
+
     def rhs(self, U, out=None):
         import torch
         out = torch.empty_like(U) if out is None else out
@@ -297,6 +314,5 @@ class Context:
     def run(self, U, nsteps: int):
         """nsteps CFL-limited steps, dt computed on the device each step."""
         for _ in range(nsteps):
-            self.dt_device(U)
-            self.step_device_dt(U)
+            self.step_cfl(U)
         return U

@@ -158,6 +158,39 @@ def test_device_dt_path_matches_host_dt(dev):
     np.testing.assert_array_equal(U.cpu().numpy(), a)
 
 
+@pytest.mark.parametrize("case", ["ragged3_runs", "short_runs", "mixed", "ragged2"])
+def test_step_cfl_matches_separate_cfl_pass(dev, case):
+    """mhd_step_cfl (in 3D the CFL reduction inside the first face kernel)
+    gives the dt of mhd_dt_device and the state of mhd_step_device_dt, bit
+    for bit, and that dt is the oracle's. ragged3_runs: 20 x 18 x 37 (z-runs of
+    16, 16, 5 planes; partial columns); short_runs: 12 x 10 x 7 (one run
+    shorter than 16); mixed: the first state in mixed precision."""
+    if case == "ragged3_runs":
+        s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
+    elif case == "short_runs":
+        s, U0 = W.generic_state(3, 12, 10, 7, "minmod", "hll", seed=5)
+    elif case == "mixed":
+        s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
+        s = dict(s, precision="mixed")
+    else:
+        s, U0 = ragged(2, "minmod", "hlld")
+    print("step_cfl", case, flush=True)
+    ctx = ctx_for(s, dev)
+    Ua = torch.from_numpy(U0).to(dev)
+    Ub = Ua.clone()
+    dta = torch.zeros(1, dtype=torch.float64, device=dev)
+    dtb = torch.zeros(1, dtype=torch.float64, device=dev)
+    for step in range(3):
+        ctx.dt_device(Ua, dta)
+        ctx.step_device_dt(Ua, dta)
+        ctx.step_cfl(Ub, dtb)
+        assert dta.item() == dtb.item(), (step, dta.item(), dtb.item())
+        np.testing.assert_array_equal(Ua.cpu().numpy(), Ub.cpu().numpy())
+        if step == 0:
+            assert dtb.item() == pytest.approx(O.dt(O.cfg_from(s), U0), rel=1e-14)
+    ctx.check()
+
+
 def test_full_size_256_sampled_parity_and_invariants(dev):
     """Full 256^3 turbulence in the configuration the benchmark times: the
     time step against the oracle on the whole grid, two steps against the
