@@ -42,10 +42,10 @@ struct RowTile {
   static constexpr int NT = TX * TY;  // workgroup size
 };
 
-// Face records (fluxes, alpha+-, HLL-weighted velocities) are stored in the
-// precision the solver computed them in: FP64, or FP32 in the mixed mode
-// (exact, and half the bytes for the EMF and update kernels). The workspace
-// holds dim * NSLOT * n doubles either way.
+// Face records (fluxes, alpha+-, HLL-weighted velocities) and edge EMFs are
+// stored in the precision they were computed in: FP64, or FP32 in the mixed
+// mode (exact, and half the bytes for the kernels that read them). The
+// workspace holds dim * NSLOT * n and 3 * n doubles either way.
 template <class R>
 __device__ __forceinline__ R* face_records(double* FW) {
   return reinterpret_cast<R*>(FW);
@@ -107,7 +107,7 @@ __device__ __forceinline__ bool row_cell(const Geom& g, const TileGrid& tg, int&
 // b-faces at A-offsets -2..+1, and v_B and b_A on the a-faces at B-offsets
 // -2..+1, each reconstructed toward the edge.
 template <int LIM, class R>
-__device__ __forceinline__ double emf_core(R apa_m, R apa_c, R ama_m, R ama_c, R apb_m, R apb_c,
+__device__ __forceinline__ R emf_core(R apa_m, R apa_c, R ama_m, R ama_c, R apb_m, R apb_c,
                                            R amb_m, R amb_c, const R* vbA, const R* bB,
                                            const R* vaB, const R* bA) {
   const R apa = max_r(apa_m, apa_c), ama = max_r(ama_m, ama_c);
@@ -117,13 +117,13 @@ __device__ __forceinline__ double emf_core(R apa_m, R apa_c, R ama_m, R ama_c, R
   edge_pair<LIM, R>(bB[0], bB[1], bB[2], bB[3], bW, bE);
   edge_pair<LIM, R>(vaB[0], vaB[1], vaB[2], vaB[3], vS, vN);
   edge_pair<LIM, R>(bA[0], bA[1], bA[2], bA[3], bS, bN);
-  return (double)uct<R>(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN);
+  return uct<R>(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN);
 }
 
 // Edge EMF of component C at cell (i,j,k): the edge at the lower A- and
 // lower B-position of the cell, (A, B) = (C+1, C+2) cyclic.
 template <int C, int LIM, class R>
-__device__ __forceinline__ double emf_comp(const double* __restrict__ U,
+__device__ __forceinline__ R emf_comp(const double* __restrict__ U,
                                            const double* __restrict__ FW, const Geom& g, int i,
                                            int j, int k, int64_t c) {
   constexpr int A = (C + 1) % 3, B = (C + 2) % 3;
@@ -175,6 +175,7 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
   const R* fx = face_records<R>(FW);
   const R* fy = fx + (int64_t)NSLOT * n;
   const R* fz = fx + (int64_t)2 * NSLOT * n;
+  R* ew = face_records<R>(EW);
   const double* bx = U + F_BX * n;
   const double* by = U + F_BY * n;
   const double* bz = U + F_BZ * n;
@@ -232,17 +233,17 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
     {
       const R wv[4] = {r[6], r[7], r[8], r[9]};
       const R wb[4] = {(R)d[2], (R)d[3], (R)d[4], (R)d[5]};
-      EW[c] = emf_core<LIM, R>(yap[0], yap[1], yam[0], yam[1], r[14], zapc, zamj, zamc, wv, wb,
+      ew[c] = emf_core<LIM, R>(yap[0], yap[1], yam[0], yam[1], r[14], zapc, zamj, zamc, wv, wb,
                                yv, yb);
     }
     // E_y: (A, B) = (z, x); a-faces are z-faces, b-faces x-faces
     {
       const R sv[4] = {r[10], r[11], r[12], r[13]};
       const R sb[4] = {(R)d[6], (R)d[7], (R)d[4], (R)d[8]};
-      EW[n + c] = emf_core<LIM, R>(zapi, zapc, zami, zamc, xap[0], xap[1], xam[0], xam[1], xv, xb,
+      ew[n + c] = emf_core<LIM, R>(zapi, zapc, zami, zamc, xap[0], xap[1], xam[0], xam[1], xv, xb,
                                    sv, sb);
     }
-    EW[2 * n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
+    ew[2 * n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       yv[s] = yv[s + 1];
@@ -264,11 +265,12 @@ __global__ __launch_bounds__(RowTile::NT) void k_emf(const double* __restrict__ 
   int i, j, k;
   if (!row_cell(g, tg, i, j, k)) return;
   const int64_t c = lin(g, i, j, k);
+  R* ew = face_records<R>(EW);
   if (DIM == 3) {
-    EW[c] = emf_comp<0, LIM, R>(U, FW, g, i, j, k, c);
-    EW[g.n + c] = emf_comp<1, LIM, R>(U, FW, g, i, j, k, c);
+    ew[c] = emf_comp<0, LIM, R>(U, FW, g, i, j, k, c);
+    ew[g.n + c] = emf_comp<1, LIM, R>(U, FW, g, i, j, k, c);
   }
-  EW[2 * g.n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
+  ew[2 * g.n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
 }
 
 // STAGE 0: out = L(U); 1: out = U + dt L(U); 2: out = (U0 + (U + dt L(U))) / 2.
@@ -302,17 +304,17 @@ __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict
     if (DIM == 3) acc += ((double)fz[q * n + zp] - (double)fz[q * n + c]) * idz;
     L[qq == 5 ? 7 : qq] = -acc;
   }
+  // edge EMFs, stored in R, widened to FP64 before differencing
+  const R* ex = face_records<R>(EW);
+  const R* ey = ex + n;
+  const R* ez = ex + 2 * n;
   if (DIM == 3) {
-    const double* ex = EW;
-    const double* ey = EW + n;
-    const double* ez = EW + 2 * n;
-    L[5] = -((ez[yp] - ez[c]) * idy - (ey[zp] - ey[c]) * idz);
-    L[6] = -((ex[zp] - ex[c]) * idz - (ez[xp] - ez[c]) * idx);
-    L[7] = -((ey[xp] - ey[c]) * idx - (ex[yp] - ex[c]) * idy);
+    L[5] = -(((double)ez[yp] - (double)ez[c]) * idy - ((double)ey[zp] - (double)ey[c]) * idz);
+    L[6] = -(((double)ex[zp] - (double)ex[c]) * idz - ((double)ez[xp] - (double)ez[c]) * idx);
+    L[7] = -(((double)ey[xp] - (double)ey[c]) * idx - ((double)ex[yp] - (double)ex[c]) * idy);
   } else {
-    const double* ez = EW + 2 * n;
-    L[5] = -((ez[yp] - ez[c]) * idy);
-    L[6] = (ez[xp] - ez[c]) * idx;
+    L[5] = -(((double)ez[yp] - (double)ez[c]) * idy);
+    L[6] = ((double)ez[xp] - (double)ez[c]) * idx;
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
