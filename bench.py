@@ -50,6 +50,10 @@ KERNEL_BOUND = {"faces": "alu", "emf": "hbm", "update": "hbm", "cfl": "hbm"}
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.0 and 1.0), for the
 # kernels as they stand; see profiles/.
 KERNEL_TRAFFIC = {"faces": 202.0 + 216.0}
+# Mixed mode: the face kernel reads the FP64 state and writes its 27 records in
+# FP32; it is bound by HBM (see profiles/), so its roofline entry is in bytes.
+KERNEL_BYTES_MIXED = {"faces": 8 * 8 + 4 * 27}
+KERNEL_TRAFFIC_MIXED = {"faces": None}
 
 
 def time_gpu(setup, U0, steps, warmup, timing=True):
@@ -274,8 +278,19 @@ def main(argv=None):
         el_m, kt_m, _, phys_m = time_gpu(sm, Um, args.steps, args.warmup)
         del Um
         vm = ncell * args.steps / el_m / 1e6
+        tot_m, nl_m = kt_m["faces"]
+        avg_m = tot_m / nl_m / 1e3
+        ach_m = KERNEL_BYTES_MIXED["faces"] * ncell / avg_m
+        tr_m = KERNEL_TRAFFIC_MIXED["faces"]
         out["mixed"] = {"value": vm, "unit": "Mcell-updates/s", "ms_per_step": el_m / args.steps * 1e3,
                         "hbm_roofline_frac_step": vm * 1e6 * STEP_BYTES / HBM_PEAK,
+                        "roofline": {"kernel": "faces", "bound": "hbm", "achieved": ach_m / 1e9,
+                                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                     "frac": ach_m / HBM_PEAK,
+                                     "traffic": tr_m * ncell if tr_m else None,
+                                     "traffic_unit": "bytes per launch",
+                                     "avg_launch_ms": avg_m * 1e3,
+                                     "bytes_per_cell": KERNEL_BYTES_MIXED["faces"]},
                         "physical": phys_m,
                         "config": {"workload": "turbulence_3d_lowbeta_%d" % args.n, "mach": 3,
                                    "beta": 0.01, "precision": "mixed"},
