@@ -49,11 +49,11 @@ KERNEL_BOUND = {"faces": "alu", "emf": "hbm", "update": "hbm", "cfl": "hbm"}
 # HBM bytes per cell of one launch measured with rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.0 and 1.0), for the
 # kernels as they stand; see profiles/.
-KERNEL_TRAFFIC = {"faces": 202.0 + 216.0}
+KERNEL_TRAFFIC = {"faces": 202.4 + 216.0}
 # Mixed mode: the face kernel reads the FP64 state and writes its 27 records in
 # FP32; it is bound by HBM (see profiles/), so its roofline entry is in bytes.
 KERNEL_BYTES_MIXED = {"faces": 8 * 8 + 4 * 27}
-KERNEL_TRAFFIC_MIXED = {"faces": None}
+KERNEL_TRAFFIC_MIXED = {"faces": 203.0 + 108.0}
 
 
 def time_gpu(setup, U0, steps, warmup, timing=True):
