@@ -10,7 +10,8 @@
 //   k_update      — per cell, flux divergence of the cell fields, -curl E of
 //                   the face fields, and the RK combination (or the bare RHS).
 // The CFL time step is a per-cell minimum reduced with wave64 shuffles and a
-// block LDS step into per-block partials, then one finishing block.
+// block LDS step into per-block partials, then one finishing block; in the 3D
+// step the first stage's face kernel computes those partials itself.
 //
 // Layout: state and workspace arrays are field-major SoA, x fastest, so a
 // wavefront of 64 consecutive cells reads 512 contiguous bytes per field.
@@ -47,12 +48,12 @@ struct RowTile {
 // mode (exact, and half the bytes for the kernels that read them). The
 // workspace holds dim * NSLOT * n and 3 * n doubles either way.
 template <class R>
-__device__ __forceinline__ R* face_records(double* FW) {
-  return reinterpret_cast<R*>(FW);
+__device__ __forceinline__ R* stored(double* buf) {
+  return reinterpret_cast<R*>(buf);
 }
 template <class R>
-__device__ __forceinline__ const R* face_records(const double* FW) {
-  return reinterpret_cast<const R*>(FW);
+__device__ __forceinline__ const R* stored(const double* buf) {
+  return reinterpret_cast<const R*>(buf);
 }
 
 struct MarchGrid {
@@ -108,8 +109,8 @@ __device__ __forceinline__ bool row_cell(const Geom& g, const TileGrid& tg, int&
 // -2..+1, each reconstructed toward the edge.
 template <int LIM, class R>
 __device__ __forceinline__ R emf_core(R apa_m, R apa_c, R ama_m, R ama_c, R apb_m, R apb_c,
-                                           R amb_m, R amb_c, const R* vbA, const R* bB,
-                                           const R* vaB, const R* bA) {
+                                      R amb_m, R amb_c, const R* vbA, const R* bB, const R* vaB,
+                                      const R* bA) {
   const R apa = max_r(apa_m, apa_c), ama = max_r(ama_m, ama_c);
   const R apb = max_r(apb_m, apb_c), amb = max_r(amb_m, amb_c);
   R vW, vE, bW, bE, vS, vN, bS, bN;
@@ -124,12 +125,12 @@ __device__ __forceinline__ R emf_core(R apa_m, R apa_c, R ama_m, R ama_c, R apb_
 // lower B-position of the cell, (A, B) = (C+1, C+2) cyclic.
 template <int C, int LIM, class R>
 __device__ __forceinline__ R emf_comp(const double* __restrict__ U,
-                                           const double* __restrict__ FW, const Geom& g, int i,
-                                           int j, int k, int64_t c) {
+                                      const double* __restrict__ FW, const Geom& g, int i, int j,
+                                      int k, int64_t c) {
   constexpr int A = (C + 1) % 3, B = (C + 2) % 3;
   const int64_t n = g.n;
-  const R* fa = face_records<R>(FW) + (int64_t)A * NSLOT * n;  // a-faces (normal A)
-  const R* fb = face_records<R>(FW) + (int64_t)B * NSLOT * n;  // b-faces (normal B)
+  const R* fa = stored<R>(FW) + (int64_t)A * NSLOT * n;  // a-faces (normal A)
+  const R* fb = stored<R>(FW) + (int64_t)B * NSLOT * n;  // b-faces (normal B)
   const int64_t cmb = shifted<B>(g, i, j, k, -1);  // a-face below the edge along B
   const int64_t cma = shifted<A>(g, i, j, k, -1);  // b-face below the edge along A
   const int64_t a2 = shifted<A>(g, i, j, k, -2), a1 = shifted<A>(g, i, j, k, 1);
@@ -172,10 +173,10 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
   const int k0 = zc * mg.lz;
   const int k1 = min(k0 + mg.lz, g.nz);
   const int64_t n = g.n;
-  const R* fx = face_records<R>(FW);
+  const R* fx = stored<R>(FW);
   const R* fy = fx + (int64_t)NSLOT * n;
   const R* fz = fx + (int64_t)2 * NSLOT * n;
-  R* ew = face_records<R>(EW);
+  R* ew = stored<R>(EW);
   const double* bx = U + F_BX * n;
   const double* by = U + F_BY * n;
   const double* bz = U + F_BZ * n;
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(RowTile::NT) void k_emf(const double* __restrict__ 
   int i, j, k;
   if (!row_cell(g, tg, i, j, k)) return;
   const int64_t c = lin(g, i, j, k);
-  R* ew = face_records<R>(EW);
+  R* ew = stored<R>(EW);
   if (DIM == 3) {
     ew[c] = emf_comp<0, LIM, R>(U, FW, g, i, j, k, c);
     ew[g.n + c] = emf_comp<1, LIM, R>(U, FW, g, i, j, k, c);
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict
   const int64_t yp = lin(g, i, wrap(j + 1, g.ny), k);
   const int64_t zp = (DIM == 3) ? lin(g, i, j, wrap(k + 1, g.nz)) : c;
   const double idx = 1.0 / g.dx, idy = 1.0 / g.dy, idz = 1.0 / g.dz;
-  const R* fx = face_records<R>(FW);
+  const R* fx = stored<R>(FW);
   const R* fy = fx + (int64_t)NSLOT * n;
   const R* fz = fx + (int64_t)2 * NSLOT * n;
   double L[8];
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict
     L[qq == 5 ? 7 : qq] = -acc;
   }
   // edge EMFs, stored in R, widened to FP64 before differencing
-  const R* ex = face_records<R>(EW);
+  const R* ex = stored<R>(EW);
   const R* ey = ex + n;
   const R* ez = ex + 2 * n;
   if (DIM == 3) {
@@ -395,7 +396,7 @@ __device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM],
   RiemannOut<R> o;
   riemann<RS, R>((R)g.gamma, wl, wr, bn, o);
   const int64_t n = g.n;
-  R* fw = face_records<R>(FW) + (int64_t)D * NSLOT * n + c;
+  R* fw = stored<R>(FW) + (int64_t)D * NSLOT * n + c;
   fw[S_RHO * n] = o.f[0];
   fw[(S_MX + D) * n] = o.f[1];
   fw[(S_MX + T1) * n] = o.f[2];
@@ -556,7 +557,7 @@ __device__ __forceinline__ void march_solve(const R* wl, const R* wr, R bn,
   RiemannOut<R> o;
   riemann<RS, R>((R)g.gamma, wl, wr, bn, o);
   const int64_t n = g.n;
-  R* fw = face_records<R>(FW) + (int64_t)D * NSLOT * n + c;
+  R* fw = stored<R>(FW) + (int64_t)D * NSLOT * n + c;
   fw[S_RHO * n] = o.f[0];
   fw[(S_MX + D) * n] = o.f[1];
   fw[(S_MX + T1) * n] = o.f[2];
