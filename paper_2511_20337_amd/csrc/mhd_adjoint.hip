@@ -411,6 +411,8 @@ struct Bufs {
   double* BC;    // 3 x n: cell-centred field cotangent
   double* T;     // 8 x n: J^T G of the cell-averaged fields
   double* A;     // 8 x n: cotangent of the stage-1 state
+  double* FWn;   // dim x NSLOT x n: face records at U_n (kept from the stage-1 forward)
+  double* EWn;   // 3 x n: edge EMFs at U_n
   double* part;  // 2 x nblocks: dtbar partial sums
 };
 
@@ -755,7 +757,7 @@ __global__ __launch_bounds__(1024) void k_sum_final(const double* __restrict__ p
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-Bufs carve(double* scratch, int64_t n) {
+Bufs carve(double* scratch, int dim, int64_t n) {
   Bufs b;
   double* p = scratch;
   b.EB = p; p += 3 * NE * n;
@@ -764,6 +766,8 @@ Bufs carve(double* scratch, int64_t n) {
   b.BC = p; p += 3 * n;
   b.T = p; p += 8 * n;
   b.A = p; p += 8 * n;
+  b.FWn = p; p += (int64_t)dim * NSLOT * n;
+  b.EWn = p; p += 3 * n;
   b.part = p;
   return b;
 }
@@ -771,24 +775,24 @@ Bufs carve(double* scratch, int64_t n) {
 // J^T of one stage, combined: out = cd Dir + s G + dt J_L(U)^T (s G); the
 // forward records FW/EW must hold the face/edge data at U.
 template <int DIM, int LIM, int RS>
-hipError_t stage_adjoint(const AdjointArgs& a, const Bufs& bf, const double* U,
-                         const double* G, double s, const double* Dir, double cd, double* out,
-                         double* part) {
+hipError_t stage_adjoint(const AdjointArgs& a, const Bufs& bf, const double* U, const double* FW,
+                         const double* EW, const double* G, double s, const double* Dir,
+                         double cd, double* out, double* part) {
   const unsigned nb = blocks_for(a.g.n);
-  hipLaunchKernelGGL((k_adj_edges<DIM, LIM>), dim3(nb), dim3(kBlock), 0, a.stream, U, a.FW, G, s,
+  hipLaunchKernelGGL((k_adj_edges<DIM, LIM>), dim3(nb), dim3(kBlock), 0, a.stream, U, FW, G, s,
                      a.g, bf.EB);
-  hipLaunchKernelGGL((k_adj_faces<DIM, LIM, RS>), dim3(nb), dim3(kBlock), 0, a.stream, U, a.FW, G,
+  hipLaunchKernelGGL((k_adj_faces<DIM, LIM, RS>), dim3(nb), dim3(kBlock), 0, a.stream, U, FW, G,
                      s, a.g, bf);
   hipLaunchKernelGGL((k_adj_cells<DIM, LIM>), dim3(nb), dim3(kBlock), 0, a.stream, U, a.g, bf);
-  hipLaunchKernelGGL((k_adj_final<DIM>), dim3(nb), dim3(kBlock), 0, a.stream, G, s, Dir, cd, a.FW,
-                     a.EW, a.g, a.dt, bf, out, part);
+  hipLaunchKernelGGL((k_adj_final<DIM>), dim3(nb), dim3(kBlock), 0, a.stream, G, s, Dir, cd, FW,
+                     EW, a.g, a.dt, bf, out, part);
   return hipGetLastError();
 }
 
 template <int DIM, int LIM, int RS>
 hipError_t adjoint_impl(const AdjointArgs& a) {
   const int64_t n = a.g.n;
-  const Bufs bf = carve(a.scratch, n);
+  const Bufs bf = carve(a.scratch, a.dim, n);
   const unsigned nb = blocks_for(n);
   StageArgs f{};
   f.dim = a.dim;
@@ -803,25 +807,29 @@ hipError_t adjoint_impl(const AdjointArgs& a) {
   f.flag = a.flag;
   f.stream = a.stream;
   f.timer = nullptr;
-  // forward stage 1: U1 = Un + dt L(Un)
+  // forward stage 1: U1 = Un + dt L(Un); its face/edge records at Un are
+  // kept (FWn, EWn) for the stage-1 adjoint
   f.stage = 1;
   f.U = a.Un;
   f.U0 = nullptr;
   f.out = a.U1;
+  f.FW = bf.FWn;
+  f.EW = bf.EWn;
   hipError_t e = launch_stage(f);
   if (e != hipSuccess) return e;
   // records at U1, then the stage-2 adjoint: A = G2 + dt J(U1)^T G2, G2 = Ubar1/2
   f.stage = 3;
   f.U = a.U1;
+  f.FW = a.FW;
+  f.EW = a.EW;
   e = launch_stage(f);
   if (e != hipSuccess) return e;
-  e = stage_adjoint<DIM, LIM, RS>(a, bf, a.U1, a.Ubar1, 0.5, nullptr, 0.0, bf.A, bf.part);
+  e = stage_adjoint<DIM, LIM, RS>(a, bf, a.U1, a.FW, a.EW, a.Ubar1, 0.5, nullptr, 0.0, bf.A,
+                                  bf.part);
   if (e != hipSuccess) return e;
-  // records at Un, then the stage-1 adjoint: Ubar0 = Ubar1/2 + A + dt J(Un)^T A
-  f.U = a.Un;
-  e = launch_stage(f);
-  if (e != hipSuccess) return e;
-  e = stage_adjoint<DIM, LIM, RS>(a, bf, a.Un, bf.A, 1.0, a.Ubar1, 0.5, a.Ubar0, bf.part + nb);
+  // the stage-1 adjoint at Un: Ubar0 = Ubar1/2 + A + dt J(Un)^T A
+  e = stage_adjoint<DIM, LIM, RS>(a, bf, a.Un, bf.FWn, bf.EWn, bf.A, 1.0, a.Ubar1, 0.5, a.Ubar0,
+                                  bf.part + nb);
   if (e != hipSuccess) return e;
   if (a.want_dtbar)
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(1024), 0, a.stream, bf.part, (int)(2 * nb),
@@ -839,9 +847,9 @@ hipError_t adjoint_dim(const AdjointArgs& a) {
 }  // namespace
 
 size_t adjoint_workspace_bytes(int dim, size_t ncell) {
-  (void)dim;
   const size_t nb = (ncell + kBlock - 1) / kBlock;
-  return sizeof(double) * ((size_t)(3 * NE + 3 * 14 + 3 + 3 + 8 + 8) * ncell + 2 * nb) + 256;
+  const size_t per_cell = 3 * NE + 3 * 14 + 3 + 3 + 8 + 8 + (size_t)dim * NSLOT + 3;
+  return sizeof(double) * (per_cell * ncell + 2 * nb) + 256;
 }
 
 hipError_t launch_adjoint_step(const AdjointArgs& a) {
