@@ -194,8 +194,10 @@ def test_step_cfl_matches_separate_cfl_pass(dev, case):
 def test_full_size_256_sampled_parity_and_invariants(dev):
     """Full 256^3 turbulence in the configuration the benchmark times: the
     time step against the oracle on the whole grid, two steps against the
-    oracle at sampled cells (corners, faces and random interior), then ten
-    more steps checked for conservation and div B on the whole grid."""
+    oracle at sampled cells (corners, faces and random interior), one step
+    of mhd_step_cfl (the benchmark's entry) against the separate CFL pass bit
+    for bit, then ten more steps checked for conservation and div B on the
+    whole grid."""
     s, U0 = W.turbulence_3d(256)
     print("256^3: dt + 2 steps", flush=True)
     ctx = ctx_for(s, dev)
@@ -216,6 +218,16 @@ def test_full_size_256_sampled_parity_and_invariants(dev):
     scale = np.abs(U0).max(axis=(1, 2, 3))
     err = (np.abs(g - ref) / scale).max(axis=0)
     assert (err <= 1e-12).all(), err
+    print("256^3: the benchmark's step entry against the separate CFL pass", flush=True)
+    Ub = U.clone()
+    dta = torch.zeros(1, dtype=torch.float64, device=dev)
+    dtb = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.dt_device(U, dta)
+    ctx.step_device_dt(U, dta)
+    ctx.step_cfl(Ub, dtb)
+    assert dta.item() == dtb.item()
+    assert torch.equal(U, Ub)
+    del Ub
     print("256^3 invariants: 10 more steps", flush=True)
     ctx.run(U, 10)
     Uf = U.cpu().numpy()
