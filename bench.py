@@ -246,7 +246,8 @@ def main(argv=None):
     roofline.update({"traffic": traffic * ncell if traffic else None,
                      "traffic_unit": "bytes per launch", "avg_launch_ms": avg_s * 1e3,
                      "flops_per_cell": KERNEL_FLOPS.get(name), "bytes_per_cell": bpc,
-                     "hbm_algorithmic_GBps": bpc * ncell / avg_s / 1e9})
+                     "hbm_algorithmic_GBps": bpc * ncell / avg_s / 1e9,
+                     "hbm_counted_GBps": traffic * ncell / avg_s / 1e9 if traffic else None})
     kernels = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "share": v[0] / sum(x[0] for x in kt.values())}
                for k, v in kt.items() if v[1]}
 
@@ -290,7 +291,8 @@ def main(argv=None):
                                      "traffic": tr_m * ncell if tr_m else None,
                                      "traffic_unit": "bytes per launch",
                                      "avg_launch_ms": avg_m * 1e3,
-                                     "bytes_per_cell": KERNEL_BYTES_MIXED["faces"]},
+                                     "bytes_per_cell": KERNEL_BYTES_MIXED["faces"],
+                                     "hbm_counted_GBps": tr_m * ncell / avg_m / 1e9 if tr_m else None},
                         "physical": phys_m,
                         "config": {"workload": "turbulence_3d_lowbeta_%d" % args.n, "mach": 3,
                                    "beta": 0.01, "precision": "mixed"},
