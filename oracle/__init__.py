@@ -27,6 +27,7 @@ _SO = os.path.join(_HERE, "libmhd_oracle.so")
 LIMITERS = {"minmod": 0, "vanleer": 1}
 SOLVERS = {"hlld": 0, "hll": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+INTEGRATORS = {"rk2": 0, "rk3": 1}
 
 
 class OCfg(ctypes.Structure):
@@ -39,6 +40,7 @@ class OCfg(ctypes.Structure):
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
         ("limiter", ctypes.c_int32), ("riemann", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("nthreads", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -117,7 +119,8 @@ def cfg_from(setup: dict, nthreads: int = 0, **over) -> OCfg:
                 box[0], box[1], box[2], box[3], box[4], box[5],
                 float(s["gamma"]), float(s["cfl"]),
                 LIMITERS[s["limiter"]], SOLVERS[s["riemann"]],
-                PRECISIONS[s.get("precision", "fp64")], int(nthreads))
+                PRECISIONS[s.get("precision", "fp64")], int(nthreads),
+                INTEGRATORS[s.get("integrator", "rk2")])
 
 
 def _shape(c: OCfg):
@@ -141,7 +144,8 @@ def rhs(c: OCfg, U, allow_unphysical=False) -> np.ndarray:
 
 
 def step(c: OCfg, U, dt: float) -> np.ndarray:
-    """One SSP-RK2 step with the given dt; returns the new state (copy)."""
+    """One SSP-RK2 (or, with integrator "rk3", SSP-RK3) step with the given
+    dt; returns the new state (copy)."""
     U = _state(c, U).copy()
     _check(_load().oracle_step(ctypes.byref(c), _ptr(U), float(dt)))
     return U

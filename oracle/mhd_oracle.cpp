@@ -147,6 +147,7 @@ struct OCfg {
   int32_t riemann;          // 0 HLLD, 1 HLL
   int32_t precision;        // 0 FP64, 1 mixed (FP32 reconstruction/Riemann/EMF)
   int32_t nthreads;         // OpenMP threads (<= 0: library default)
+  int32_t integrator;       // 0 SSP-RK2, 1 SSP-RK3
 };
 
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4, BX = 5, BY = 6, BZ = 7, NF = 8 };
@@ -589,6 +590,30 @@ int rk2_step(const OCfg& cfg, S* U, S dt, RhsFn rhs) {
   return bad;
 }
 
+// SSP-RK3 of Shu & Osher, Sec. 2.2 Eq. (RK3) [reading: the printed last stage
+// adds L** once where the scheme's third order needs it twice; L = dt times
+// the right-hand side]: U* = Un + dt L(Un);
+// U** = (3 Un + (U* + dt L(U*))) / 4;  Un+1 = (Un + 2 (U** + dt L(U**))) / 3.
+template <class S, class RhsFn>
+int rk3_step(const OCfg& cfg, S* U, S dt, RhsFn rhs) {
+  const Grid G(cfg);
+  const size_t N = (size_t)NF * G.ncell;
+  std::vector<S> L(N), U1(N), U2(N);
+  int bad = rhs(U, L.data());
+  for (size_t q = 0; q < N; ++q) U1[q] = U[q] + dt * L[q];
+  bad |= rhs(U1.data(), L.data());
+  for (size_t q = 0; q < N; ++q) U2[q] = (S(3) * U[q] + (U1[q] + dt * L[q])) / S(4);
+  bad |= rhs(U2.data(), L.data());
+  for (size_t q = 0; q < N; ++q) U[q] = (U[q] + S(2) * (U2[q] + dt * L[q])) / S(3);
+  return bad;
+}
+
+// One step with the configured integrator.
+template <class S, class RhsFn>
+int ssp_step(const OCfg& cfg, S* U, S dt, RhsFn rhs) {
+  return cfg.integrator == 1 ? rk3_step<S>(cfg, U, dt, rhs) : rk2_step<S>(cfg, U, dt, rhs);
+}
+
 // CFL time step [reading: the paper gives no formula]:
 // dt = C min over cells and directions of Delta_d / (|v_d| + c_f,d).
 int cfl_dt(const OCfg& cfg, const double* U, double* dt_out) {
@@ -638,6 +663,7 @@ bool cfg_ok(const OCfg* c) {
   if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return false;
   if (c->limiter < 0 || c->limiter > 1 || c->riemann < 0 || c->riemann > 1) return false;
   if (c->precision < 0 || c->precision > 1) return false;
+  if (c->integrator < 0 || c->integrator > 1) return false;
   if (!(c->xmax > c->xmin) || !(c->ymax > c->ymin) || !(c->zmax > c->zmin)) return false;
   return true;
 }
@@ -656,7 +682,7 @@ int oracle_rhs(const OCfg* cfg, const double* U, double* L) {
 
 int oracle_step(const OCfg* cfg, double* U, double dt) {
   if (!cfg_ok(cfg) || !U || !(dt > 0.0) || !std::isfinite(dt)) return -1;
-  int bad = rk2_step<double>(*cfg, U, dt, [&](const double* u, double* l) {
+  int bad = ssp_step<double>(*cfg, U, dt, [&](const double* u, double* l) {
     return rhs_dispatch<double, double>(*cfg, u, l);
   });
   return bad ? -4 : 0;
@@ -676,7 +702,7 @@ int oracle_run(const OCfg* cfg, double* U, int nsteps, double* dts) {
     double dt;
     bad |= cfl_dt(*cfg, U, &dt);
     if (dts) dts[s] = dt;
-    bad |= rk2_step<double>(*cfg, U, dt, [&](const double* u, double* l) {
+    bad |= ssp_step<double>(*cfg, U, dt, [&](const double* u, double* l) {
       return rhs_dispatch<double, double>(*cfg, u, l);
     });
   }
@@ -688,7 +714,7 @@ int oracle_run_dts(const OCfg* cfg, double* U, int nsteps, const double* dts) {
   if (!cfg_ok(cfg) || !U || nsteps < 0 || !dts) return -1;
   int bad = 0;
   for (int s = 0; s < nsteps; ++s) {
-    bad |= rk2_step<double>(*cfg, U, dts[s], [&](const double* u, double* l) {
+    bad |= ssp_step<double>(*cfg, U, dts[s], [&](const double* u, double* l) {
       return rhs_dispatch<double, double>(*cfg, u, l);
     });
   }
@@ -705,7 +731,7 @@ int oracle_step_jvp(const OCfg* cfg, double* U, double* dU, double dt, double dd
   const size_t N = (size_t)NF * G.ncell;
   std::vector<Dual> Ud(N);
   for (size_t q = 0; q < N; ++q) Ud[q] = Dual(U[q], dU[q]);
-  int bad = rk2_step<Dual>(c, Ud.data(), Dual(dt, ddt), [&](const Dual* u, Dual* l) {
+  int bad = ssp_step<Dual>(c, Ud.data(), Dual(dt, ddt), [&](const Dual* u, Dual* l) {
     return compute_rhs<Dual, Dual>(c, u, l);
   });
   for (size_t q = 0; q < N; ++q) { U[q] = Ud[q].v; dU[q] = Ud[q].d; }
