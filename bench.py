@@ -326,6 +326,15 @@ def main(argv=None):
                               "hardware": "NVIDIA H100 (4 per node)",
                               "scheme": "WENO-Z + RK3 + HLLD + CT, FP64",
                               "note": "context only: another scheme on other hardware"}}
+        log("the same with SSP-RK3, the paper's integrator")
+        so3, Uo3 = W.orszag_tang_3d(352)
+        so3 = dict(so3, integrator="rk3")
+        el_o3, kt_o3, _, phys_o3 = time_gpu(so3, Uo3, steps_o, 1)
+        del Uo3
+        out["orszag_tang_3d"]["rk3"] = {
+            "value": 352 ** 3 * steps_o / el_o3 / 1e6, "unit": "Mcell-updates/s",
+            "ms_per_step": el_o3 / steps_o * 1e3, "physical": phys_o3,
+            "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_o3.items() if v[1]}}
         log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, checkpoints every 8")
         adj, fwd = time_adjoint(512, 64, 8)
         out["adjoint"] = {"value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,

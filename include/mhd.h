@@ -61,6 +61,9 @@ typedef enum { MHD_RS_HLLD = 0, MHD_RS_HLL = 1 } mhd_riemann;
  * recovery (incl. pressure), flux/curl differencing, the RK combination and
  * the time step in FP64. The state is FP64 in both modes. */
 typedef enum { MHD_PREC_FP64 = 0, MHD_PREC_MIXED = 1 } mhd_precision;
+/* Time integrator: the two-stage SSP Runge-Kutta scheme, or the three-stage
+ * one of Sec. 2.2 Eq. (RK3) (Shu & Osher). */
+typedef enum { MHD_SSP_RK2 = 0, MHD_SSP_RK3 = 1 } mhd_integrator;
 
 typedef struct {
   int32_t dim;                  /* 2 or 3 */
@@ -71,7 +74,7 @@ typedef struct {
   int32_t limiter;              /* mhd_limiter */
   int32_t riemann;              /* mhd_riemann */
   int32_t precision;            /* mhd_precision */
-  int32_t reserved;             /* must be 0 */
+  int32_t integrator;           /* mhd_integrator (0, the former reserved field, is SSP-RK2) */
 } mhd_config;
 
 typedef struct mhd_ctx mhd_ctx;
@@ -99,8 +102,11 @@ mhd_status mhd_dt(mhd_ctx* ctx, const double* U, void* ws, size_t ws_bytes, doub
 mhd_status mhd_dt_device(mhd_ctx* ctx, const double* U, void* ws, size_t ws_bytes, double* dt_dev,
                          void* stream);
 
-/* One SSP-RK2 step of size dt, in place:
- *   U1 = U + dt L(U);  U <- (U + (U1 + dt L(U1))) / 2,
+/* One step of size dt, in place. SSP-RK2:
+ *   U1 = U + dt L(U);  U <- (U + (U1 + dt L(U1))) / 2;
+ * SSP-RK3 (Sec. 2.2 Eq. (RK3), read as the Shu-Osher scheme):
+ *   U1 = U + dt L(U);  U2 = (3 U + (U1 + dt L(U1))) / 4;
+ *   U <- (U + 2 (U2 + dt L(U2))) / 3,
  * with L the finite-volume right-hand side (Eq. FV) for the cell fields and
  * -curl E on the faces for the staggered field. dt must be > 0 and finite. */
 mhd_status mhd_step(mhd_ctx* ctx, double* U, double dt, void* ws, size_t ws_bytes, void* stream);
@@ -128,7 +134,8 @@ mhd_status mhd_rhs(mhd_ctx* ctx, const double* U, double* L, void* ws, size_t ws
  * non-NULL, the host double *dtbar = (dPhi/d dt)^T Ubar_np1 (this one
  * synchronises). Not part of the paper: the derivative of every
  * non-smooth point (limiter at extrema, min/max, Riemann region switches) is
- * that of the branch the forward step takes. FP64 only. Ubar_n must not
+ * that of the branch the forward step takes. FP64 and SSP-RK2 only
+ * (MHD_ERR_UNSUPPORTED otherwise). Ubar_n must not
  * alias Ubar_np1 or U_n. Needs mhd_workspace_bytes(ctx, 1). */
 mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const double* Ubar_np1,
                             double* Ubar_n, double* dtbar, void* ws, size_t ws_bytes,

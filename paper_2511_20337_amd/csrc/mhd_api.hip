@@ -94,7 +94,7 @@ struct mhd_ctx {
   EventTimer* timer;
   mhd::Geom g;
   // workspace layout (byte offsets from the 256-aligned base)
-  size_t off_partial, off_u1, off_fw, off_ew, off_adj, bytes_fwd, bytes_adj;
+  size_t off_partial, off_u1, off_fw, off_ew, off_u2, off_adj, bytes_fwd, bytes_adj;
   int cfl_blocks;
   char err[256];
 };
@@ -117,7 +117,8 @@ bool cfg_valid(const mhd_config* c) {
   if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) return false;
   if (!(c->cfl > 0.0) || !std::isfinite(c->cfl)) return false;
   if (c->limiter < 0 || c->limiter > 1 || c->riemann < 0 || c->riemann > 1) return false;
-  if (c->precision < 0 || c->precision > 1 || c->reserved != 0) return false;
+  if (c->precision < 0 || c->precision > 1) return false;
+  if (c->integrator != MHD_SSP_RK2 && c->integrator != MHD_SSP_RK3) return false;
   // 64-bit cell count; per-axis sizes bounded so index arithmetic stays in int
   const double cells = (double)c->nx * c->ny * c->nz;
   if (cells > 4.0e9) return false;
@@ -153,8 +154,8 @@ mhd::StageArgs stage_args(mhd_ctx* ctx, void* ws, hipStream_t s) {
   return a;
 }
 
-// One RK2 step. dt_cfl (3D only): dt is the CFL step of U, reduced by the
-// stage-1 face kernel and written to dt_cfl, which is also dtp.
+// One SSP-RK2 or SSP-RK3 step. dt_cfl (3D only): dt is the CFL step of U,
+// reduced by the stage-1 face kernel and written to dt_cfl, which is also dtp.
 mhd_status run_step(mhd_ctx* ctx, double* U, double dt, const double* dtp, void* ws,
                     hipStream_t s, double* dt_cfl = nullptr) {
   double* U1 = reinterpret_cast<double*>(base(ws) + ctx->off_u1);
@@ -173,6 +174,22 @@ mhd_status run_step(mhd_ctx* ctx, double* U, double dt, const double* dtp, void*
   hipError_t e = mhd::launch_stage(a);
   if (e != hipSuccess) return device_fail(ctx, e, "stage 1");
   a.cfl_partial = nullptr;
+  if (ctx->cfg.integrator == MHD_SSP_RK3) {
+    double* U2 = reinterpret_cast<double*>(base(ws) + ctx->off_u2);
+    a.stage = 4;  // U2 = (3 U + (U1 + dt L(U1))) / 4
+    a.U = U1;
+    a.U0 = U;
+    a.out = U2;
+    e = mhd::launch_stage(a);
+    if (e != hipSuccess) return device_fail(ctx, e, "stage 2");
+    a.stage = 5;  // U <- (U + 2 (U2 + dt L(U2))) / 3
+    a.U = U2;
+    a.U0 = U;
+    a.out = U;
+    e = mhd::launch_stage(a);
+    if (e != hipSuccess) return device_fail(ctx, e, "stage 3");
+    return MHD_OK;
+  }
   a.stage = 2;
   a.U = U1;
   a.U0 = U;
@@ -246,6 +263,8 @@ mhd_status mhd_init(const mhd_config* cfg, mhd_ctx** out) {
   off = align_up(off + sizeof(double) * (size_t)cfg->dim * mhd::NSLOT * n);
   c->off_ew = off;
   off = align_up(off + sizeof(double) * 3 * n);
+  c->off_u2 = off;  // SSP-RK3: the second-stage state
+  if (cfg->integrator == MHD_SSP_RK3) off = align_up(off + sizeof(double) * 8 * n);
   c->bytes_fwd = off;
   c->off_adj = off;
   c->bytes_adj = off + mhd::adjoint_workspace_bytes(cfg->dim, n);
@@ -339,7 +358,8 @@ static mhd_status adjoint_impl(mhd_ctx* ctx, const double* U_n, double dt, const
   if (!ctx) return MHD_ERR_INVALID;
   if (!U_n || !Ubar_np1 || !Ubar_n || !(dt > 0.0) || !std::isfinite(dt)) return MHD_ERR_INVALID;
   if (Ubar_n == Ubar_np1 || Ubar_n == U_n) return MHD_ERR_INVALID;
-  if (ctx->cfg.precision != MHD_PREC_FP64) return MHD_ERR_UNSUPPORTED;
+  if (ctx->cfg.precision != MHD_PREC_FP64 || ctx->cfg.integrator != MHD_SSP_RK2)
+    return MHD_ERR_UNSUPPORTED;
   if (!ws_ok(ctx, ws, ws_bytes, true)) return MHD_ERR_WORKSPACE;
   mhd::AdjointArgs a{};
   a.dim = ctx->cfg.dim;

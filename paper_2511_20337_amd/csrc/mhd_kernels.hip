@@ -274,7 +274,9 @@ __global__ __launch_bounds__(RowTile::NT) void k_emf(const double* __restrict__ 
   ew[2 * g.n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
 }
 
-// STAGE 0: out = L(U); 1: out = U + dt L(U); 2: out = (U0 + (U + dt L(U))) / 2.
+// STAGE 0: out = L(U); 1: out = U + dt L(U); 2: out = (U0 + (U + dt L(U))) / 2
+// (SSP-RK2); 4: out = (3 U0 + (U + dt L(U))) / 4 and 5: out = (U0 + 2 (U + dt
+// L(U))) / 3, the second and third stages of SSP-RK3 (Eq. (RK3)).
 // R: the precision of the stored fluxes (differenced in FP64).
 template <int DIM, int STAGE, class R>
 __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict__ U,
@@ -322,6 +324,8 @@ __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict
     double v;
     if (STAGE == 0) v = L[q];
     else if (STAGE == 1) v = U[q * n + c] + h * L[q];
+    else if (STAGE == 4) v = (3.0 * U0[q * n + c] + (U[q * n + c] + h * L[q])) / 4.0;
+    else if (STAGE == 5) v = (U0[q * n + c] + 2.0 * (U[q * n + c] + h * L[q])) / 3.0;
     else v = 0.5 * (U0[q * n + c] + (U[q * n + c] + h * L[q]));
     out[q * n + c] = v;
   }
@@ -859,6 +863,16 @@ hipError_t stage_impl(const StageArgs& a) {
     case 1:
       MHD_TIMED(a, K_UPDATE,
                 hipLaunchKernelGGL((k_update<DIM, 1, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                                   a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
+      break;
+    case 4:
+      MHD_TIMED(a, K_UPDATE,
+                hipLaunchKernelGGL((k_update<DIM, 4, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                                   a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
+      break;
+    case 5:
+      MHD_TIMED(a, K_UPDATE,
+                hipLaunchKernelGGL((k_update<DIM, 5, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                    a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
       break;
     default:

@@ -21,7 +21,8 @@ struct Timer {
 struct StageArgs {
   int dim, limiter, riemann, precision;
   int stage;              // 0: out = L(U); 1: out = U + dt L; 2: out = (U0 + U + dt L)/2;
-                          // 3: face/edge records only
+                          // 3: face/edge records only; SSP-RK3 stages 2 and 3:
+                          // 4: out = (3 U0 + (U + dt L))/4; 5: out = (U0 + 2 (U + dt L))/3
   Geom g;
   const double* U;        // state the right-hand side is evaluated at
   const double* U0;       // stage 2: state at the start of the step

@@ -26,6 +26,7 @@ MHD_ERR_WORKSPACE = -5
 LIMITERS = {"minmod": 0, "vanleer": 1}
 SOLVERS = {"hlld": 0, "hll": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+INTEGRATORS = {"rk2": 0, "rk3": 1}
 
 # Every symbol include/mhd.h declares.
 SYMBOLS = ("mhd_init", "mhd_destroy", "mhd_workspace_bytes", "mhd_dt", "mhd_dt_device",
@@ -43,7 +44,7 @@ class mhd_config(ctypes.Structure):  # noqa: N801 — C name
         ("zmin", ctypes.c_double), ("zmax", ctypes.c_double),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
         ("limiter", ctypes.c_int32), ("riemann", ctypes.c_int32),
-        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("integrator", ctypes.c_int32),
     ]
 
 
@@ -109,7 +110,8 @@ def config_from(setup: dict) -> mhd_config:
     return mhd_config(int(setup["dim"]), int(setup["nx"]), int(setup["ny"]), int(setup["nz"]),
                       b[0], b[1], b[2], b[3], b[4], b[5], float(setup["gamma"]),
                       float(setup["cfl"]), LIMITERS[setup["limiter"]], SOLVERS[setup["riemann"]],
-                      PRECISIONS[setup.get("precision", "fp64")], 0)
+                      PRECISIONS[setup.get("precision", "fp64")],
+                      INTEGRATORS[setup.get("integrator", "rk2")])
 
 
 # ---------------------------------------------------------------- C names --

@@ -149,6 +149,28 @@ def test_ten_step_parity_fp64(dev, case):
     assert (err <= 1e-12).all(), err
 
 
+@pytest.mark.parametrize("case", ["ragged3_runs", "orszag_tang_128", "mixed"])
+def test_ten_step_parity_rk3(dev, case):
+    """SSP-RK3 (Eq. (RK3)): ten CFL steps against the oracle's SSP-RK3, FP64
+    to 1e-12 per field; in mixed precision against the oracle's mixed
+    variant with the mixed path's stated bound (2e-5)."""
+    if case == "ragged3_runs":
+        s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
+    elif case == "orszag_tang_128":
+        s, U0 = W.orszag_tang_2d(128)
+    else:
+        s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
+        s = dict(s, precision="mixed")
+    s = dict(s, integrator="rk3")
+    print("rk3 10-step parity", case, flush=True)
+    ctx = ctx_for(s, dev)
+    got, dts = _run_gpu(ctx, U0, 10, dev)
+    ref, odts = O.run(O.cfg_from(s), U0, 10)
+    np.testing.assert_allclose(dts, odts, rtol=1e-13 if case != "mixed" else 1e-6)
+    err = rel_err(got, ref if case != "mixed" else O.run_dts(O.cfg_from(s), U0, dts))
+    assert (err <= (1e-12 if case != "mixed" else 2e-5)).all(), err
+
+
 def test_orszag_tang_3d_ten_step_parity(dev):
     """The paper's 3D Orszag-Tang problem (its first benchmark) at 32^3, ten
     CFL steps of this path's scheme against the oracle."""
@@ -193,7 +215,7 @@ def test_device_dt_path_matches_host_dt(dev):
     np.testing.assert_array_equal(U.cpu().numpy(), a)
 
 
-@pytest.mark.parametrize("case", ["ragged3_runs", "short_runs", "mixed", "ragged2"])
+@pytest.mark.parametrize("case", ["ragged3_runs", "short_runs", "mixed", "ragged2", "rk3"])
 def test_step_cfl_matches_separate_cfl_pass(dev, case):
     """mhd_step_cfl (in 3D the CFL reduction inside the first face kernel)
     gives the dt of mhd_dt_device and the state of mhd_step_device_dt, bit
@@ -207,6 +229,9 @@ def test_step_cfl_matches_separate_cfl_pass(dev, case):
     elif case == "mixed":
         s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
         s = dict(s, precision="mixed")
+    elif case == "rk3":
+        s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
+        s = dict(s, integrator="rk3")
     else:
         s, U0 = ragged(2, "minmod", "hlld")
     print("step_cfl", case, flush=True)

@@ -33,7 +33,7 @@ def test_init_validates_config():
     assert mhd.mhd_workspace_bytes(ctx, True) >= fwd
     mhd.mhd_destroy(ctx)
     bad = [("dim", 4), ("nx", 3), ("nz", 2), ("gamma", 1.0), ("cfl", 0.0), ("cfl", float("nan")),
-           ("xmax", 0.0), ("limiter", 2), ("riemann", -1), ("precision", 3), ("reserved", 1)]
+           ("xmax", 0.0), ("limiter", 2), ("riemann", -1), ("precision", 3), ("integrator", 2)]
     for field, value in bad:
         cfg = mhd.config_from(s)
         setattr(cfg, field, value)
