@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mhd_oracle.cpp")
 _SO = os.path.join(_HERE, "libmhd_oracle.so")
 
-LIMITERS = {"minmod": 0, "vanleer": 1}
+LIMITERS = {"minmod": 0, "vanleer": 1, "wenoz": 2}
 SOLVERS = {"hlld": 0, "hll": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 INTEGRATORS = {"rk2": 0, "rk3": 1}
@@ -79,6 +79,7 @@ def _load():
                                 ctypes.c_double, dp], ctypes.c_int),
             ("oracle_flux", [ctypes.c_double, dp, ctypes.c_double, dp, dp], ctypes.c_int),
             ("oracle_slope", [ctypes.c_int, ctypes.c_double, ctypes.c_double], ctypes.c_double),
+            ("oracle_wenoz", [ctypes.POINTER(ctypes.c_double)], ctypes.c_double),
             ("oracle_fast_speed", [ctypes.c_double] * 6, ctypes.c_double),
             ("oracle_uct", [dp], ctypes.c_double),
             ("oracle_count_ops", [cp, dp, P(ctypes.c_longlong)], ctypes.c_int),
@@ -224,6 +225,13 @@ def flux(w, bn, gamma=5.0 / 3.0):
 
 def slope(limiter: str, dm: float, dp: float) -> float:
     return float(_load().oracle_slope(LIMITERS[limiter], float(dm), float(dp)))
+
+
+def wenoz(v) -> float:
+    """WENO-Z value at the upper interface of the middle of five cell values."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.shape == (5,)
+    return float(_load().oracle_wenoz(_ptr(v)))
 
 
 def fast_speed(gamma, rho, p, bn, bt1, bt2) -> float:

@@ -143,7 +143,7 @@ struct OCfg {
   double xmin, xmax, ymin, ymax, zmin, zmax;
   double gamma;             // adiabatic index
   double cfl;               // Courant number
-  int32_t limiter;          // 0 minmod, 1 van Leer
+  int32_t limiter;          // 0 minmod, 1 van Leer (PLM); 2 WENO-Z
   int32_t riemann;          // 0 HLLD, 1 HLL
   int32_t precision;        // 0 FP64, 1 mixed (FP32 reconstruction/Riemann/EMF)
   int32_t nthreads;         // OpenMP threads (<= 0: library default)
@@ -208,6 +208,33 @@ template <class R> R limited_slope(int limiter, R dm, R dp) {
   if (dm * dp <= R(0)) return R(0);
   if (limiter == 0) return (Abs(dm) <= Abs(dp)) ? dm : dp;        // minmod
   return R(2) * dm * dp / (dm + dp);                              // van Leer
+}
+
+// Fifth-order WENO-Z value at the upper interface of the middle cell of five
+// (v0..v4 = cells i-2..i+2), after Borges et al. (2008), cited with Eq.
+// (reconstruct) [reading: the paper gives no formulas; the three third-order
+// candidate values, the Jiang-Shu smoothness indicators beta_k, the ideal
+// weights (1, 6, 3)/10, tau5 = |beta0 - beta2| and the Z weights
+// alpha_k = d_k (1 + tau5 / (beta_k + eps)) with the exponent 1 and
+// eps = 1e-40]. The lower interface value is the same function of the cells
+// in reverse order.
+template <class R> R wenoz_upper(R v0, R v1, R v2, R v3, R v4) {
+  const R q0 = (R(2) * v0 - R(7) * v1 + R(11) * v2) / R(6);
+  const R q1 = (-v1 + R(5) * v2 + R(2) * v3) / R(6);
+  const R q2 = (R(2) * v2 + R(5) * v3 - v4) / R(6);
+  const R c1 = R(13) / R(12), c2 = R(1) / R(4);
+  const R a0 = v0 - R(2) * v1 + v2, b0 = v0 - R(4) * v1 + R(3) * v2;
+  const R a1 = v1 - R(2) * v2 + v3, b1 = v1 - v3;
+  const R a2 = v2 - R(2) * v3 + v4, b2 = R(3) * v2 - R(4) * v3 + v4;
+  const R beta0 = c1 * a0 * a0 + c2 * b0 * b0;
+  const R beta1 = c1 * a1 * a1 + c2 * b1 * b1;
+  const R beta2 = c1 * a2 * a2 + c2 * b2 * b2;
+  const R tau5 = Abs(beta0 - beta2);
+  const R eps = R(1e-40);
+  const R al0 = R(0.1) * (R(1) + tau5 / (beta0 + eps));
+  const R al1 = R(0.6) * (R(1) + tau5 / (beta1 + eps));
+  const R al2 = R(0.3) * (R(1) + tau5 / (beta2 + eps));
+  return (al0 * q0 + al1 * q1 + al2 * q2) / (al0 + al1 + al2);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,14 +480,21 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
         for (int i = 0; i < G.nx; ++i) {
           const size_t cm2 = G.shift(i, j, k, d, -2), cm1 = G.shift(i, j, k, d, -1);
           const size_t c0 = G.at(i, j, k), cp1 = G.shift(i, j, k, d, +1);
+          const size_t cm3 = G.shift(i, j, k, d, -3), cp2 = G.shift(i, j, k, d, +2);
           R wl[7], wr[7];
           for (int q = 0; q < 7; ++q) {
             const S* P = Vf(slot[q]);
             const R a = Cast<R>::of(P[cm2]), b = Cast<R>::of(P[cm1]);
             const R c = Cast<R>::of(P[c0]), e = Cast<R>::of(P[cp1]);
             // face i-1/2: left state from cell i-1, right state from cell i
-            wl[q] = b + R(0.5) * limited_slope(cfg.limiter, b - a, c - b);
-            wr[q] = c - R(0.5) * limited_slope(cfg.limiter, c - b, e - c);
+            if (cfg.limiter == 2) {
+              const R z = Cast<R>::of(P[cm3]), f = Cast<R>::of(P[cp2]);
+              wl[q] = wenoz_upper(z, a, b, c, e);
+              wr[q] = wenoz_upper(f, e, c, b, a);
+            } else {
+              wl[q] = b + R(0.5) * limited_slope(cfg.limiter, b - a, c - b);
+              wr[q] = c - R(0.5) * limited_slope(cfg.limiter, c - b, e - c);
+            }
           }
           const R bn = Cast<R>::of(F(BX + d)[c0]);  // staggered normal field
           RSOut<R> o;
@@ -505,8 +539,10 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
             const R xm1 = get(G.shift(i, j, k, e, -1));
             const R x0 = get(c0);
             const R xp1 = get(G.shift(i, j, k, e, +1));
-            lo = xm1 + R(0.5) * limited_slope(cfg.limiter, xm1 - xm2, x0 - xm1);
-            hi = x0 - R(0.5) * limited_slope(cfg.limiter, x0 - xm1, xp1 - x0);
+            // [reading: with WENO-Z faces, the edge values use van Leer PLM]
+            const int el = cfg.limiter == 2 ? 1 : cfg.limiter;
+            lo = xm1 + R(0.5) * limited_slope(el, xm1 - xm2, x0 - xm1);
+            hi = x0 - R(0.5) * limited_slope(el, x0 - xm1, xp1 - x0);
           };
           // a-faces touching the edge: cells c0 - e_b and c0
           const size_t ca = G.shift(i, j, k, b, -1);
@@ -661,7 +697,7 @@ bool cfg_ok(const OCfg* c) {
   if (c->dim == 3 && c->nz < 4) return false;
   if (c->dim == 2 && c->nz != 1) return false;
   if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return false;
-  if (c->limiter < 0 || c->limiter > 1 || c->riemann < 0 || c->riemann > 1) return false;
+  if (c->limiter < 0 || c->limiter > 2 || c->riemann < 0 || c->riemann > 1) return false;
   if (c->precision < 0 || c->precision > 1) return false;
   if (c->integrator < 0 || c->integrator > 1) return false;
   if (!(c->xmax > c->xmin) || !(c->ymax > c->ymin) || !(c->zmax > c->zmin)) return false;
@@ -833,6 +869,9 @@ int oracle_flux(double gamma, const double* w, double bn, double* U7, double* F7
 double oracle_slope(int limiter, double dm, double dp) {
   return limited_slope<double>(limiter, dm, dp);
 }
+
+// WENO-Z upper-interface value of the middle of five cell values (for unit tests).
+double oracle_wenoz(const double* v) { return wenoz_upper<double>(v[0], v[1], v[2], v[3], v[4]); }
 
 double oracle_fast_speed(double gamma, double rho, double p, double bn, double bt1, double bt2) {
   return fast_speed<double>(gamma, rho, p, bn, bt1, bt2);

@@ -277,3 +277,25 @@ def test_unphysical_state_reported():
         O.step(c, U, 1e-3)
     with pytest.raises(O.OracleError):
         O.step(c, U, -1.0)
+
+
+def test_wenoz_pins():
+    """WENO-Z (Borges et al. 2008, cited with Eq. (reconstruct)): linear data
+    are reproduced exactly, odd symmetry, a step adds no new extremum and takes
+    the value of its smooth side, and the upper-interface value of smooth cell
+    averages converges at fifth order (exp: exact averages, exact point value)."""
+    assert O.wenoz([1.0, 2.0, 3.0, 4.0, 5.0]) == pytest.approx(3.5, abs=1e-14)
+    assert O.wenoz([-0.7, -0.4, -0.1, 0.2, 0.5]) == pytest.approx(0.05, abs=1e-14)
+    v = [0.3, -1.2, 2.5, 0.7, -0.4]
+    assert O.wenoz([-x for x in v]) == pytest.approx(-O.wenoz(v), abs=1e-15)
+    for step, side in (([0, 0, 0, 1, 1], 0.0), ([0, 0, 1, 1, 1], 1.0), ([1, 1, 0, 0, 0], 0.0)):
+        val = O.wenoz([float(x) for x in step])
+        assert abs(val - side) <= 1e-12, (step, val)
+    errs = []
+    for h in (0.1, 0.05, 0.025, 0.0125):
+        avg = [(math.exp(0.3 + (k + 0.5) * h) - math.exp(0.3 + (k - 0.5) * h)) / h
+               for k in (-2, -1, 0, 1, 2)]
+        errs.append(abs(O.wenoz(avg) - math.exp(0.3 + 0.5 * h)))
+    orders = [math.log2(errs[q] / errs[q + 1]) for q in range(3)]
+    assert min(orders) >= 4.9, (errs, orders)
+
