@@ -55,7 +55,10 @@ typedef enum {
   MHD_ERR_WORKSPACE = -5     /* workspace missing or too small */
 } mhd_status;
 
-typedef enum { MHD_LIM_MINMOD = 0, MHD_LIM_VANLEER = 1 } mhd_limiter;
+/* Reconstruction: PLM with the minmod or van Leer limiter, or fifth-order
+ * WENO-Z (Borges et al. 2008, cited with Eq. (reconstruct); FP64 only, with van
+ * Leer PLM for the CT edge values; the adjoint does not support it). */
+typedef enum { MHD_LIM_MINMOD = 0, MHD_LIM_VANLEER = 1, MHD_LIM_WENOZ = 2 } mhd_limiter;
 typedef enum { MHD_RS_HLLD = 0, MHD_RS_HLL = 1 } mhd_riemann;
 /* MHD_PREC_MIXED: reconstruction, Riemann solve and EMF in FP32; primitive
  * recovery (incl. pressure), flux/curl differencing, the RK combination and
@@ -134,7 +137,7 @@ mhd_status mhd_rhs(mhd_ctx* ctx, const double* U, double* L, void* ws, size_t ws
  * non-NULL, the host double *dtbar = (dPhi/d dt)^T Ubar_np1 (this one
  * synchronises). Not part of the paper: the derivative of every
  * non-smooth point (limiter at extrema, min/max, Riemann region switches) is
- * that of the branch the forward step takes. FP64 and SSP-RK2 only
+ * that of the branch the forward step takes. FP64, PLM and SSP-RK2 only
  * (MHD_ERR_UNSUPPORTED otherwise). Ubar_n must not
  * alias Ubar_np1 or U_n. Needs mhd_workspace_bytes(ctx, 1). */
 mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const double* Ubar_np1,

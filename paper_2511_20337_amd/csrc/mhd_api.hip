@@ -116,7 +116,8 @@ bool cfg_valid(const mhd_config* c) {
   if (!(c->xmax > c->xmin) || !(c->ymax > c->ymin) || !(c->zmax > c->zmin)) return false;
   if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) return false;
   if (!(c->cfl > 0.0) || !std::isfinite(c->cfl)) return false;
-  if (c->limiter < 0 || c->limiter > 1 || c->riemann < 0 || c->riemann > 1) return false;
+  if (c->limiter < 0 || c->limiter > 2 || c->riemann < 0 || c->riemann > 1) return false;
+  if (c->limiter == MHD_LIM_WENOZ && c->precision != MHD_PREC_FP64) return false;
   if (c->precision < 0 || c->precision > 1) return false;
   if (c->integrator != MHD_SSP_RK2 && c->integrator != MHD_SSP_RK3) return false;
   // 64-bit cell count; per-axis sizes bounded so index arithmetic stays in int
@@ -329,8 +330,9 @@ mhd_status mhd_step_cfl(mhd_ctx* ctx, double* U, double* dt_dev, void* ws, size_
   if (!U || !dt_dev) return MHD_ERR_INVALID;
   if (!ws_ok(ctx, ws, ws_bytes, false)) return MHD_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (ctx->cfg.dim == 3) return run_step(ctx, U, 0.0, dt_dev, ws, s, dt_dev);
-  mhd_status st = cfl_to(ctx, U, ws, dt_dev, s);  // 2D: the separate CFL pass
+  if (ctx->cfg.dim == 3 && ctx->cfg.limiter != MHD_LIM_WENOZ)
+    return run_step(ctx, U, 0.0, dt_dev, ws, s, dt_dev);
+  mhd_status st = cfl_to(ctx, U, ws, dt_dev, s);  // 2D and WENO-Z: the separate CFL pass
   if (st != MHD_OK) return st;
   return run_step(ctx, U, 0.0, dt_dev, ws, s);
 }
@@ -358,7 +360,8 @@ static mhd_status adjoint_impl(mhd_ctx* ctx, const double* U_n, double dt, const
   if (!ctx) return MHD_ERR_INVALID;
   if (!U_n || !Ubar_np1 || !Ubar_n || !(dt > 0.0) || !std::isfinite(dt)) return MHD_ERR_INVALID;
   if (Ubar_n == Ubar_np1 || Ubar_n == U_n) return MHD_ERR_INVALID;
-  if (ctx->cfg.precision != MHD_PREC_FP64 || ctx->cfg.integrator != MHD_SSP_RK2)
+  if (ctx->cfg.precision != MHD_PREC_FP64 || ctx->cfg.integrator != MHD_SSP_RK2 ||
+      ctx->cfg.limiter == MHD_LIM_WENOZ)
     return MHD_ERR_UNSUPPORTED;
   if (!ws_ok(ctx, ws, ws_bytes, true)) return MHD_ERR_WORKSPACE;
   mhd::AdjointArgs a{};

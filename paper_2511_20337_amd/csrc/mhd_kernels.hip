@@ -448,6 +448,64 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
 }
 
 // ---------------------------------------------------------------------------
+// Lower face of direction D of cell (i,j,k) with WENO-Z reconstruction (FP64):
+// the six cells along D (offsets -3..+2) are recovered straight from the
+// state; the left state is the upper value of cell -1 (cells -3..+1), the
+// right state the lower value of cell 0 (cells +2..-2 in reverse).
+template <int DIM, int D, int RS>
+__device__ __forceinline__ bool weno_face(const double* __restrict__ U, double* __restrict__ FW,
+                                          const Geom& g, int i, int j, int k, int64_t c) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  constexpr int slot[7] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4};
+  double V[6][8];
+  bool ok = true;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int o = s - 3;
+    ok &= prim_at<DIM>(U, g, D == 0 ? wrap_any(i + o, g.nx) : i, D == 1 ? wrap_any(j + o, g.ny) : j,
+                       D == 2 ? wrap_any(k + o, g.nz) : k, V[s]);
+  }
+  double wl[7], wr[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int sq = slot[q];
+    wl[q] = wenoz_upper(V[0][sq], V[1][sq], V[2][sq], V[3][sq], V[4][sq]);
+    wr[q] = wenoz_upper(V[5][sq], V[4][sq], V[3][sq], V[2][sq], V[1][sq]);
+  }
+  const int64_t n = g.n;
+  RiemannOut<double> o;
+  riemann<RS, double>(g.gamma, wl, wr, U[(F_BX + D) * n + c], o);
+  double* fw = FW + (int64_t)D * NSLOT * n + c;
+  fw[S_RHO * n] = o.f[0];
+  fw[(S_MX + D) * n] = o.f[1];
+  fw[(S_MX + T1) * n] = o.f[2];
+  fw[(S_MX + T2) * n] = o.f[3];
+  fw[S_EN * n] = o.f[6];
+  if (DIM == 2) fw[S_BZ * n] = (D == 0) ? o.f[5] : o.f[4];  // B_z is t2 of x, t1 of y
+  fw[S_AP * n] = o.ap;
+  fw[S_AM * n] = o.am;
+  fw[S_V1 * n] = o.v1;
+  fw[S_V2 * n] = o.v2;
+  return ok;
+}
+
+// Face kernel for WENO-Z (2D and 3D, FP64), one cell per thread on row tiles:
+// its ±3-cell stencils are gathered from the state through the caches rather
+// than staged in LDS (a z-march ring would need five planes and a 3-cell halo).
+template <int DIM, int RS>
+__global__ __launch_bounds__(RowTile::NT) void k_faces_weno(const double* __restrict__ U,
+                                                       double* __restrict__ FW, Geom g,
+                                                       TileGrid tg, int* __restrict__ flag) {
+  int i, j, k;
+  if (!row_cell(g, tg, i, j, k)) return;
+  const int64_t c = lin(g, i, j, k);
+  bool ok = weno_face<DIM, 0, RS>(U, FW, g, i, j, k, c);
+  ok &= weno_face<DIM, 1, RS>(U, FW, g, i, j, k, c);
+  if (DIM == 3) ok &= weno_face<DIM, 2, RS>(U, FW, g, i, j, k, c);
+  if (!ok) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
 // 3D face kernel marching along z. A workgroup owns a 64 x 4 column of cells
 // and walks a run of planes k0 <= k < k1, one cell of each plane per thread.
 // LDS holds the primitives of planes k-1, k, k+1 of the column (a ring of
@@ -820,9 +878,17 @@ MarchGrid march_grid(const Geom& g) {
 
 template <int DIM, int LIM, int RS, class R>
 hipError_t stage_impl(const StageArgs& a) {
+  // LIM 2 (WENO-Z, FP64): faces by k_faces_weno, edge values by van Leer PLM
+  constexpr int ELIM = (LIM == 2) ? 1 : LIM;
   const TileGrid rg = tile_grid<RowTile>(a.g);
   const unsigned nb = rg.ntiles;
-  if constexpr (DIM == 3) {
+  if constexpr (LIM == 2) {
+    static_assert(sizeof(R) == 8, "WENO-Z runs in FP64");
+    if (a.cfl_partial) return hipErrorInvalidValue;  // the CFL is not fused here
+    MHD_TIMED(a, K_FACES,
+              hipLaunchKernelGGL((k_faces_weno<DIM, RS>), dim3(nb), dim3(RowTile::NT), 0, a.stream,
+                                 a.U, a.FW, a.g, rg, a.flag));
+  } else if constexpr (DIM == 3) {
     const MarchGrid mg = march_grid(a.g);
     MHD_TIMED(a, K_FACES,
               hipLaunchKernelGGL((k_faces_march<LIM, RS, R>), dim3(mg.nblocks), dim3(kBlock), 0,
@@ -845,11 +911,11 @@ hipError_t stage_impl(const StageArgs& a) {
     eg.nzc = (a.g.nz + eg.lz - 1) / eg.lz;
     eg.nblocks = (unsigned)eg.ntx * (unsigned)eg.nty * (unsigned)eg.nzc;
     MHD_TIMED(a, K_EMF,
-              hipLaunchKernelGGL((k_emf_march<LIM, R>), dim3(eg.nblocks), dim3(EmfCol::NT), 0,
+              hipLaunchKernelGGL((k_emf_march<ELIM, R>), dim3(eg.nblocks), dim3(EmfCol::NT), 0,
                                  a.stream, a.U, a.FW, a.EW, a.g, eg));
   } else {
     MHD_TIMED(a, K_EMF,
-              hipLaunchKernelGGL((k_emf<DIM, LIM, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+              hipLaunchKernelGGL((k_emf<DIM, ELIM, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                  a.FW, a.EW, a.g, rg));
   }
   switch (a.stage) {
@@ -887,6 +953,10 @@ hipError_t stage_impl(const StageArgs& a) {
 template <int DIM>
 hipError_t stage_lim(const StageArgs& a) {
   const bool mixed = a.precision == 1;
+  if (a.limiter == 2) {  // WENO-Z: FP64 only
+    if (mixed) return hipErrorInvalidValue;
+    return a.riemann == 0 ? stage_impl<DIM, 2, 0, double>(a) : stage_impl<DIM, 2, 1, double>(a);
+  }
   if (a.limiter == 0) {
     if (a.riemann == 0)
       return mixed ? stage_impl<DIM, 0, 0, float>(a) : stage_impl<DIM, 0, 0, double>(a);

@@ -23,7 +23,7 @@ MHD_ERR_DEVICE = -3
 MHD_ERR_UNPHYSICAL = -4
 MHD_ERR_WORKSPACE = -5
 
-LIMITERS = {"minmod": 0, "vanleer": 1}
+LIMITERS = {"minmod": 0, "vanleer": 1, "wenoz": 2}
 SOLVERS = {"hlld": 0, "hll": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 INTEGRATORS = {"rk2": 0, "rk3": 1}

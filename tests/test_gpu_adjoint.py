@@ -153,10 +153,11 @@ def test_adjoint_rejects_bad_arguments(dev):
     with pytest.raises(mhd.MHDError) as e:
         cm.adjoint_step(Ug, 1e-3, ub)
     assert e.value.status == mhd.MHD_ERR_UNSUPPORTED
-    c3 = mhd.Context(dict(s, integrator="rk3"), dev, with_adjoint=True)  # SSP-RK2 only
-    with pytest.raises(mhd.MHDError) as e:
-        c3.adjoint_step(Ug, 1e-3, ub)
-    assert e.value.status == mhd.MHD_ERR_UNSUPPORTED
+    for over in ({"integrator": "rk3"}, {"limiter": "wenoz"}):  # PLM + SSP-RK2 only
+        c3 = mhd.Context(dict(s, **over), dev, with_adjoint=True)
+        with pytest.raises(mhd.MHDError) as e:
+            c3.adjoint_step(Ug, 1e-3, ub)
+        assert e.value.status == mhd.MHD_ERR_UNSUPPORTED
 
 
 def test_multistep_gradient_checkpoint_invariant(dev):

@@ -88,7 +88,7 @@ def ragged(dim, lim, solver, precision="fp64"):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("lim", ["minmod", "vanleer"])
+@pytest.mark.parametrize("lim", ["minmod", "vanleer", "wenoz"])
 @pytest.mark.parametrize("solver", ["hlld", "hll"])
 def test_rhs_parity_fp64(dev, dim, lim, solver):
     s, U = ragged(dim, lim, solver)
@@ -149,7 +149,7 @@ def test_ten_step_parity_fp64(dev, case):
     assert (err <= 1e-12).all(), err
 
 
-@pytest.mark.parametrize("case", ["ragged3_runs", "orszag_tang_128", "mixed"])
+@pytest.mark.parametrize("case", ["ragged3_runs", "orszag_tang_128", "mixed", "wenoz3", "wenoz2"])
 def test_ten_step_parity_rk3(dev, case):
     """SSP-RK3 (Eq. (RK3)): ten CFL steps against the oracle's SSP-RK3, FP64
     to 1e-12 per field; in mixed precision against the oracle's mixed
@@ -158,9 +158,13 @@ def test_ten_step_parity_rk3(dev, case):
         s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
     elif case == "orszag_tang_128":
         s, U0 = W.orszag_tang_2d(128)
-    else:
+    elif case == "mixed":
         s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
         s = dict(s, precision="mixed")
+    elif case == "wenoz3":  # the paper's scheme: WENO-Z + RK3 + HLLD + CT
+        s, U0 = W.generic_state(3, 20, 18, 37, "wenoz", "hlld", seed=9)
+    else:
+        s, U0 = W.orszag_tang_2d(128, limiter="wenoz")
     s = dict(s, integrator="rk3")
     print("rk3 10-step parity", case, flush=True)
     ctx = ctx_for(s, dev)
@@ -215,7 +219,7 @@ def test_device_dt_path_matches_host_dt(dev):
     np.testing.assert_array_equal(U.cpu().numpy(), a)
 
 
-@pytest.mark.parametrize("case", ["ragged3_runs", "short_runs", "mixed", "ragged2", "rk3"])
+@pytest.mark.parametrize("case", ["ragged3_runs", "short_runs", "mixed", "ragged2", "rk3", "wenoz"])
 def test_step_cfl_matches_separate_cfl_pass(dev, case):
     """mhd_step_cfl (in 3D the CFL reduction inside the first face kernel)
     gives the dt of mhd_dt_device and the state of mhd_step_device_dt, bit
@@ -232,6 +236,8 @@ def test_step_cfl_matches_separate_cfl_pass(dev, case):
     elif case == "rk3":
         s, U0 = W.generic_state(3, 20, 18, 37, "vanleer", "hlld", seed=9)
         s = dict(s, integrator="rk3")
+    elif case == "wenoz":
+        s, U0 = W.generic_state(3, 20, 18, 37, "wenoz", "hlld", seed=9)
     else:
         s, U0 = ragged(2, "minmod", "hlld")
     print("step_cfl", case, flush=True)

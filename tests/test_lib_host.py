@@ -33,13 +33,19 @@ def test_init_validates_config():
     assert mhd.mhd_workspace_bytes(ctx, True) >= fwd
     mhd.mhd_destroy(ctx)
     bad = [("dim", 4), ("nx", 3), ("nz", 2), ("gamma", 1.0), ("cfl", 0.0), ("cfl", float("nan")),
-           ("xmax", 0.0), ("limiter", 2), ("riemann", -1), ("precision", 3), ("integrator", 2)]
+           ("xmax", 0.0), ("limiter", 3), ("riemann", -1), ("precision", 3), ("integrator", 2)]
     for field, value in bad:
         cfg = mhd.config_from(s)
         setattr(cfg, field, value)
         with pytest.raises(mhd.MHDError) as e:
             mhd.mhd_init(cfg)
         assert e.value.status == mhd.MHD_ERR_INVALID, field
+    # WENO-Z runs in FP64 only
+    cfg = mhd.config_from(dict(s, limiter="wenoz", precision="mixed"))
+    with pytest.raises(mhd.MHDError) as e:
+        mhd.mhd_init(cfg)
+    assert e.value.status == mhd.MHD_ERR_INVALID
+    mhd.mhd_destroy(mhd.mhd_init(mhd.config_from(dict(s, limiter="wenoz"))))
     s2, _ = W.orszag_tang_2d(8)
     cfg = mhd.config_from(s2)
     cfg.nz = 4  # 2D needs nz == 1
