@@ -335,6 +335,15 @@ def main(argv=None):
             "value": 352 ** 3 * steps_o / el_o3 / 1e6, "unit": "Mcell-updates/s",
             "ms_per_step": el_o3 / steps_o * 1e3, "physical": phys_o3,
             "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_o3.items() if v[1]}}
+        log("the same with the paper's scheme: WENO-Z + SSP-RK3 + HLLD + CT")
+        sow, Uow = W.orszag_tang_3d(352, limiter="wenoz")
+        sow = dict(sow, integrator="rk3")
+        el_ow, kt_ow, _, phys_ow = time_gpu(sow, Uow, steps_o, 1)
+        del Uow
+        out["orszag_tang_3d"]["wenoz_rk3"] = {
+            "value": 352 ** 3 * steps_o / el_ow / 1e6, "unit": "Mcell-updates/s",
+            "ms_per_step": el_ow / steps_o * 1e3, "physical": phys_ow,
+            "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_ow.items() if v[1]}}
         log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, checkpoints every 8")
         adj, fwd = time_adjoint(512, 64, 8)
         out["adjoint"] = {"value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
