@@ -177,6 +177,13 @@ def only_part(part, n, steps, warmup):
         out = {"part": part, "value": n ** 3 * steps / el / 1e6, "unit": "Mcell-updates/s",
                "workload": "turbulence_3d_lowbeta_%d" % n, "physical": phys,
                "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]}}
+    elif part == "ot3d_wenoz":
+        so, Uo = W.orszag_tang_3d(n, limiter="wenoz")
+        el, kt, _, phys = time_gpu(dict(so, integrator="rk3"), Uo, steps, warmup)
+        out = {"part": part, "value": n ** 3 * steps / el / 1e6, "unit": "Mcell-updates/s",
+               "workload": "orszag_tang_3d_%d wenoz ssp_rk3 hlld" % n, "physical": phys,
+               "ms_per_step": el / steps * 1e3,
+               "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]}}
     elif part == "adjoint":
         adj, fwd = time_adjoint(512, 64, 8)
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
@@ -203,7 +210,7 @@ def main(argv=None):
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters) and exit")
-    ap.add_argument("--only", choices=("mixed", "adjoint", "adjoint_3d"), default=None,
+    ap.add_argument("--only", choices=("mixed", "ot3d_wenoz", "adjoint", "adjoint_3d"), default=None,
                     help="run only this extra measurement and print it (for profiling)")
     args = ap.parse_args(argv)
     if args.copy_probe:

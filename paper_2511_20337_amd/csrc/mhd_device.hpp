@@ -120,26 +120,32 @@ __device__ __forceinline__ R plm_slope(R dm, R dp) {
 // third-order candidate values with Z weights d_k (1 + tau5 / (beta_k + eps)),
 // Jiang-Shu smoothness indicators beta_k, tau5 = |beta0 - beta2|, ideal
 // weights (1, 6, 3)/10, eps = 1e-40. The lower interface value is the same
-// function of the cells in reverse order. Plain IEEE operations, in the
-// order written, so that the result is the rounding of these expressions.
+// function of the cells in reverse order. The weights are formed over a common
+// denominator, which moves the result by a few ulps from the textbook order of
+// operations (measured: at most 3.5 ulps of the largest input).
 __device__ __forceinline__ double wenoz_upper(double v0, double v1, double v2, double v3,
                                               double v4) {
-  const double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) / 6.0;
-  const double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) / 6.0;
-  const double q2 = (2.0 * v2 + 5.0 * v3 - v4) / 6.0;
+  // six times the three candidate values
+  const double q0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
+  const double q1 = -v1 + 5.0 * v2 + 2.0 * v3;
+  const double q2 = 2.0 * v2 + 5.0 * v3 - v4;
   const double c1 = 13.0 / 12.0, c2 = 1.0 / 4.0;
   const double a0 = v0 - 2.0 * v1 + v2, b0 = v0 - 4.0 * v1 + 3.0 * v2;
   const double a1 = v1 - 2.0 * v2 + v3, b1 = v1 - v3;
   const double a2 = v2 - 2.0 * v3 + v4, b2 = 3.0 * v2 - 4.0 * v3 + v4;
-  const double beta0 = c1 * a0 * a0 + c2 * b0 * b0;
-  const double beta1 = c1 * a1 * a1 + c2 * b1 * b1;
-  const double beta2 = c1 * a2 * a2 + c2 * b2 * b2;
-  const double tau5 = __builtin_fabs(beta0 - beta2);
   const double eps = 1e-40;
-  const double al0 = 0.1 * (1.0 + tau5 / (beta0 + eps));
-  const double al1 = 0.6 * (1.0 + tau5 / (beta1 + eps));
-  const double al2 = 0.3 * (1.0 + tau5 / (beta2 + eps));
-  return (al0 * q0 + al1 * q1 + al2 * q2) / (al0 + al1 + al2);
+  const double beta0 = c1 * a0 * a0 + c2 * b0 * b0 + eps;
+  const double beta1 = c1 * a1 * a1 + c2 * b1 * b1 + eps;
+  const double beta2 = c1 * a2 * a2 + c2 * b2 * b2 + eps;
+  const double tau5 = __builtin_fabs(beta0 - beta2);
+  // d_k (1 + tau5 / beta_k) times beta0 beta1 beta2 (> 0, which the
+  // normalisation cancels), so that one division remains instead of seven;
+  // beta_k >= eps keeps the products normal, and they stay finite while the
+  // differences of the five values are below about 1e50
+  const double al0 = 0.1 * (beta0 + tau5) * (beta1 * beta2);
+  const double al1 = 0.6 * (beta1 + tau5) * (beta0 * beta2);
+  const double al2 = 0.3 * (beta2 + tau5) * (beta0 * beta1);
+  return (al0 * q0 + al1 * q1 + al2 * q2) / (6.0 * (al0 + al1 + al2));
 }
 
 // Face-frame primitive state: (rho, u_n, v_t1, v_t2, B_t1, B_t2, p).
