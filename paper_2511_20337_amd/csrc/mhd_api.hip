@@ -16,7 +16,7 @@
 namespace {
 
 const char* const kKernelNames[mhd::K_COUNT] = {"faces", "emf", "update", "cfl", "cfl_final",
-                                                "adjoint"};
+                                                "adjoint", "prim"};
 
 // Per-kernel HIP-event timing: an event pair per launch, read back on demand.
 struct EventTimer final : mhd::Timer {
@@ -94,7 +94,7 @@ struct mhd_ctx {
   EventTimer* timer;
   mhd::Geom g;
   // workspace layout (byte offsets from the 256-aligned base)
-  size_t off_partial, off_u1, off_fw, off_ew, off_u2, off_adj, bytes_fwd, bytes_adj;
+  size_t off_partial, off_u1, off_fw, off_ew, off_u2, off_pw, off_adj, bytes_fwd, bytes_adj;
   int cfl_blocks;
   char err[256];
 };
@@ -149,6 +149,8 @@ mhd::StageArgs stage_args(mhd_ctx* ctx, void* ws, hipStream_t s) {
   a.g = ctx->g;
   a.FW = reinterpret_cast<double*>(base(ws) + ctx->off_fw);
   a.EW = reinterpret_cast<double*>(base(ws) + ctx->off_ew);
+  a.PW = ctx->cfg.limiter == MHD_LIM_WENOZ
+             ? reinterpret_cast<double*>(base(ws) + ctx->off_pw) : nullptr;
   a.flag = ws_flag(ws);
   a.stream = s;
   a.timer = ctx->timer;
@@ -266,6 +268,8 @@ mhd_status mhd_init(const mhd_config* cfg, mhd_ctx** out) {
   off = align_up(off + sizeof(double) * 3 * n);
   c->off_u2 = off;  // SSP-RK3: the second-stage state
   if (cfg->integrator == MHD_SSP_RK3) off = align_up(off + sizeof(double) * 8 * n);
+  c->off_pw = off;  // WENO-Z: the primitives of every cell
+  if (cfg->limiter == MHD_LIM_WENOZ) off = align_up(off + sizeof(double) * 8 * n);
   c->bytes_fwd = off;
   c->off_adj = off;
   c->bytes_adj = off + mhd::adjoint_workspace_bytes(cfg->dim, n);

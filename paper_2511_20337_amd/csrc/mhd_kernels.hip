@@ -448,31 +448,53 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
 }
 
 // ---------------------------------------------------------------------------
-// Lower face of direction D of cell (i,j,k) with WENO-Z reconstruction (FP64):
-// the six cells along D (offsets -3..+2) are recovered straight from the
-// state; the left state is the upper value of cell -1 (cells -3..+1), the
-// right state the lower value of cell 0 (cells +2..-2 in reverse).
+// Primitive recovery for WENO-Z (FP64): every cell's primitives, in the order
+// of prim_at, into PW[8][n], so that the face kernel reads each of the six
+// cells of a stencil instead of recovering it again (each cell is in 18
+// stencils in 3D).
+template <int DIM>
+__global__ __launch_bounds__(RowTile::NT) void k_prim_weno(const double* __restrict__ U,
+                                                      double* __restrict__ PW, Geom g,
+                                                      TileGrid tg, int* __restrict__ flag) {
+  int i, j, k;
+  if (!row_cell(g, tg, i, j, k)) return;
+  const int64_t c = lin(g, i, j, k);
+  double V[8];
+  const bool ok = prim_at<DIM>(U, g, i, j, k, V);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) PW[q * g.n + c] = V[q];
+  if (!ok) atomicOr(flag, 1);
+}
+
+// Lower face of direction D of cell (i,j,k) with WENO-Z reconstruction (FP64)
+// from the primitives PW of the six cells along D (offsets -3..+2): the left
+// state is the upper value of cell -1 (cells -3..+1), the right state the
+// lower value of cell 0 (cells +2..-2 in reverse). One quantity at a time, so
+// that only its six values are live beside the reconstructed states.
 template <int DIM, int D, int RS>
-__device__ __forceinline__ bool weno_face(const double* __restrict__ U, double* __restrict__ FW,
+__device__ __forceinline__ void weno_face(const double* __restrict__ PW,
+                                          const double* __restrict__ U, double* __restrict__ FW,
                                           const Geom& g, int i, int j, int k, int64_t c) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   constexpr int slot[7] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4};
-  double V[6][8];
-  bool ok = true;
+  const int64_t n = g.n;
+  int64_t cs[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     const int o = s - 3;
-    ok &= prim_at<DIM>(U, g, D == 0 ? wrap_any(i + o, g.nx) : i, D == 1 ? wrap_any(j + o, g.ny) : j,
-                       D == 2 ? wrap_any(k + o, g.nz) : k, V[s]);
+    cs[s] = lin(g, D == 0 ? wrap_any(i + o, g.nx) : i, D == 1 ? wrap_any(j + o, g.ny) : j,
+                D == 2 ? wrap_any(k + o, g.nz) : k);
   }
   double wl[7], wr[7];
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
-    const int sq = slot[q];
-    wl[q] = wenoz_upper(V[0][sq], V[1][sq], V[2][sq], V[3][sq], V[4][sq]);
-    wr[q] = wenoz_upper(V[5][sq], V[4][sq], V[3][sq], V[2][sq], V[1][sq]);
+    const double* w = PW + slot[q] * n;
+    double v[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) v[s] = w[cs[s]];
+    wl[q] = wenoz_upper(v[0], v[1], v[2], v[3], v[4]);
+    wr[q] = wenoz_upper(v[5], v[4], v[3], v[2], v[1]);
   }
-  const int64_t n = g.n;
   RiemannOut<double> o;
   riemann<RS, double>(g.gamma, wl, wr, U[(F_BX + D) * n + c], o);
   double* fw = FW + (int64_t)D * NSLOT * n + c;
@@ -486,23 +508,23 @@ __device__ __forceinline__ bool weno_face(const double* __restrict__ U, double* 
   fw[S_AM * n] = o.am;
   fw[S_V1 * n] = o.v1;
   fw[S_V2 * n] = o.v2;
-  return ok;
 }
 
 // Face kernel for WENO-Z (2D and 3D, FP64), one cell per thread on row tiles:
-// its ±3-cell stencils are gathered from the state through the caches rather
-// than staged in LDS (a z-march ring would need five planes and a 3-cell halo).
+// its +-3-cell stencils are gathered from the primitives PW through the caches
+// rather than staged in LDS (a z-march ring would need six planes and a
+// 3-cell halo).
 template <int DIM, int RS>
-__global__ __launch_bounds__(RowTile::NT) void k_faces_weno(const double* __restrict__ U,
+__global__ __launch_bounds__(RowTile::NT) void k_faces_weno(const double* __restrict__ PW,
+                                                       const double* __restrict__ U,
                                                        double* __restrict__ FW, Geom g,
-                                                       TileGrid tg, int* __restrict__ flag) {
+                                                       TileGrid tg) {
   int i, j, k;
   if (!row_cell(g, tg, i, j, k)) return;
   const int64_t c = lin(g, i, j, k);
-  bool ok = weno_face<DIM, 0, RS>(U, FW, g, i, j, k, c);
-  ok &= weno_face<DIM, 1, RS>(U, FW, g, i, j, k, c);
-  if (DIM == 3) ok &= weno_face<DIM, 2, RS>(U, FW, g, i, j, k, c);
-  if (!ok) atomicOr(flag, 1);
+  weno_face<DIM, 0, RS>(PW, U, FW, g, i, j, k, c);
+  weno_face<DIM, 1, RS>(PW, U, FW, g, i, j, k, c);
+  if (DIM == 3) weno_face<DIM, 2, RS>(PW, U, FW, g, i, j, k, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -884,10 +906,13 @@ hipError_t stage_impl(const StageArgs& a) {
   const unsigned nb = rg.ntiles;
   if constexpr (LIM == 2) {
     static_assert(sizeof(R) == 8, "WENO-Z runs in FP64");
-    if (a.cfl_partial) return hipErrorInvalidValue;  // the CFL is not fused here
+    if (a.cfl_partial || !a.PW) return hipErrorInvalidValue;  // the CFL is not fused here
+    MHD_TIMED(a, K_PRIM,
+              hipLaunchKernelGGL((k_prim_weno<DIM>), dim3(nb), dim3(RowTile::NT), 0, a.stream,
+                                 a.U, a.PW, a.g, rg, a.flag));
     MHD_TIMED(a, K_FACES,
               hipLaunchKernelGGL((k_faces_weno<DIM, RS>), dim3(nb), dim3(RowTile::NT), 0, a.stream,
-                                 a.U, a.FW, a.g, rg, a.flag));
+                                 a.PW, a.U, a.FW, a.g, rg));
   } else if constexpr (DIM == 3) {
     const MarchGrid mg = march_grid(a.g);
     MHD_TIMED(a, K_FACES,

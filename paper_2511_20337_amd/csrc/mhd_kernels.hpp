@@ -8,7 +8,7 @@
 namespace mhd {
 
 // Kernel identities for the optional per-kernel event timing.
-enum KernelId : int { K_FACES = 0, K_EMF, K_UPDATE, K_CFL, K_CFL_FINAL, K_ADJ, K_COUNT };
+enum KernelId : int { K_FACES = 0, K_EMF, K_UPDATE, K_CFL, K_CFL_FINAL, K_ADJ, K_PRIM, K_COUNT };
 
 // Records a pair of HIP events around each launch on the launch stream.
 struct Timer {
@@ -29,6 +29,7 @@ struct StageArgs {
   double* out;
   double* FW;             // face records: dim * NSLOT * n doubles
   double* EW;             // edge EMFs: 3 * n doubles
+  double* PW;             // WENO-Z only: primitives of every cell, 8 * n doubles
   double dt;
   const double* dtp;      // device dt (nullptr: use dt)
   int* flag;              // sticky unphysical flag
