@@ -448,17 +448,32 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
 }
 
 // ---------------------------------------------------------------------------
+// Cell of this thread when each workgroup of kBlock threads takes kBlock
+// consecutive cells in storage order (x fastest), so that no lane idles
+// whatever nx is (row tiles of 64 leave 8% of the lanes idle at nx = 352).
+// The configuration check keeps n below 2^32.
+__device__ __forceinline__ bool linear_cell(const Geom& g, int& i, int& j, int& k, int64_t& c) {
+  const uint32_t t = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
+  if ((int64_t)t >= g.n) return false;
+  const uint32_t r = t / (uint32_t)g.nx;
+  i = (int)(t - r * (uint32_t)g.nx);
+  k = (int)(r / (uint32_t)g.ny);
+  j = (int)(r - (uint32_t)k * (uint32_t)g.ny);
+  c = t;
+  return true;
+}
+
 // Primitive recovery for WENO-Z (FP64): every cell's primitives, in the order
 // of prim_at, into PW[8][n], so that the face kernel reads each of the six
 // cells of a stencil instead of recovering it again (each cell is in 18
 // stencils in 3D).
 template <int DIM>
-__global__ __launch_bounds__(RowTile::NT) void k_prim_weno(const double* __restrict__ U,
-                                                      double* __restrict__ PW, Geom g,
-                                                      TileGrid tg, int* __restrict__ flag) {
+__global__ __launch_bounds__(kBlock) void k_prim_weno(const double* __restrict__ U,
+                                                 double* __restrict__ PW, Geom g,
+                                                 int* __restrict__ flag) {
   int i, j, k;
-  if (!row_cell(g, tg, i, j, k)) return;
-  const int64_t c = lin(g, i, j, k);
+  int64_t c;
+  if (!linear_cell(g, i, j, k, c)) return;
   double V[8];
   const bool ok = prim_at<DIM>(U, g, i, j, k, V);
 #pragma unroll
@@ -510,18 +525,17 @@ __device__ __forceinline__ void weno_face(const double* __restrict__ PW,
   fw[S_V2 * n] = o.v2;
 }
 
-// Face kernel for WENO-Z (2D and 3D, FP64), one cell per thread on row tiles:
-// its +-3-cell stencils are gathered from the primitives PW through the caches
-// rather than staged in LDS (a z-march ring would need six planes and a
-// 3-cell halo).
+// Face kernel for WENO-Z (2D and 3D, FP64), one cell per thread, kBlock
+// consecutive cells per workgroup: its +-3-cell stencils are gathered from the
+// primitives PW through the caches rather than staged in LDS (a z-march ring
+// would need six planes and a 3-cell halo).
 template <int DIM, int RS>
-__global__ __launch_bounds__(RowTile::NT) void k_faces_weno(const double* __restrict__ PW,
-                                                       const double* __restrict__ U,
-                                                       double* __restrict__ FW, Geom g,
-                                                       TileGrid tg) {
+__global__ __launch_bounds__(kBlock) void k_faces_weno(const double* __restrict__ PW,
+                                                  const double* __restrict__ U,
+                                                  double* __restrict__ FW, Geom g) {
   int i, j, k;
-  if (!row_cell(g, tg, i, j, k)) return;
-  const int64_t c = lin(g, i, j, k);
+  int64_t c;
+  if (!linear_cell(g, i, j, k, c)) return;
   weno_face<DIM, 0, RS>(PW, U, FW, g, i, j, k, c);
   weno_face<DIM, 1, RS>(PW, U, FW, g, i, j, k, c);
   if (DIM == 3) weno_face<DIM, 2, RS>(PW, U, FW, g, i, j, k, c);
@@ -907,12 +921,13 @@ hipError_t stage_impl(const StageArgs& a) {
   if constexpr (LIM == 2) {
     static_assert(sizeof(R) == 8, "WENO-Z runs in FP64");
     if (a.cfl_partial || !a.PW) return hipErrorInvalidValue;  // the CFL is not fused here
+    const unsigned nl = (unsigned)((a.g.n + kBlock - 1) / kBlock);
     MHD_TIMED(a, K_PRIM,
-              hipLaunchKernelGGL((k_prim_weno<DIM>), dim3(nb), dim3(RowTile::NT), 0, a.stream,
-                                 a.U, a.PW, a.g, rg, a.flag));
+              hipLaunchKernelGGL((k_prim_weno<DIM>), dim3(nl), dim3(kBlock), 0, a.stream, a.U,
+                                 a.PW, a.g, a.flag));
     MHD_TIMED(a, K_FACES,
-              hipLaunchKernelGGL((k_faces_weno<DIM, RS>), dim3(nb), dim3(RowTile::NT), 0, a.stream,
-                                 a.PW, a.U, a.FW, a.g, rg));
+              hipLaunchKernelGGL((k_faces_weno<DIM, RS>), dim3(nl), dim3(kBlock), 0, a.stream,
+                                 a.PW, a.U, a.FW, a.g));
   } else if constexpr (DIM == 3) {
     const MarchGrid mg = march_grid(a.g);
     MHD_TIMED(a, K_FACES,
