@@ -254,9 +254,10 @@ mhd_status mhd_init(const mhd_config* cfg, mhd_ctx** out) {
   c->g.gamma = cfg->gamma;
   const size_t n = (size_t)c->g.n;
   c->cfl_blocks = kCflBlocks;
-  // CFL partials: of k_cfl, or (3D) one per face workgroup of the fused step
+  // CFL partials: of k_cfl, or (3D) one per face (WENO-Z: primitive) workgroup
+  // of the fused step
   size_t npart = kCflBlocks;
-  if (cfg->dim == 3) npart = std::max(npart, mhd::stage_cfl_blocks(c->g));
+  if (cfg->dim == 3) npart = std::max(npart, mhd::stage_cfl_blocks(c->g, cfg->limiter));
   size_t off = kCtl;
   c->off_partial = off;
   off = align_up(off + sizeof(double) * npart);
@@ -334,9 +335,8 @@ mhd_status mhd_step_cfl(mhd_ctx* ctx, double* U, double* dt_dev, void* ws, size_
   if (!U || !dt_dev) return MHD_ERR_INVALID;
   if (!ws_ok(ctx, ws, ws_bytes, false)) return MHD_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (ctx->cfg.dim == 3 && ctx->cfg.limiter != MHD_LIM_WENOZ)
-    return run_step(ctx, U, 0.0, dt_dev, ws, s, dt_dev);
-  mhd_status st = cfl_to(ctx, U, ws, dt_dev, s);  // 2D and WENO-Z: the separate CFL pass
+  if (ctx->cfg.dim == 3) return run_step(ctx, U, 0.0, dt_dev, ws, s, dt_dev);
+  mhd_status st = cfl_to(ctx, U, ws, dt_dev, s);  // 2D: the separate CFL pass
   if (st != MHD_OK) return st;
   return run_step(ctx, U, 0.0, dt_dev, ws, s);
 }

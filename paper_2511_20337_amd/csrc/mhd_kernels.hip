@@ -448,6 +448,40 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
 }
 
 // ---------------------------------------------------------------------------
+// CFL bound of one cell from its FP64 primitives: min over directions of
+// dx_d / (|v_d| + c_f,d), the expression of k_cfl.
+__device__ __forceinline__ double cfl_bound(const Geom& g, const double* W, double m) {
+  const double dd[3] = {g.dx, g.dy, g.dz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double cf = cfast<double>(g.gamma, W[0], W[4], W[5 + d], W[5 + (d + 1) % 3],
+                                    W[5 + (d + 2) % 3]);
+    const double t = dd[d] / (__builtin_fabs(W[1 + d]) + cf);
+    m = (t < m) ? t : m;
+  }
+  return m;
+}
+
+// Minimum of v over the kBlock threads of the workgroup, stored by thread 0
+// to *out. Every thread of the workgroup must call it.
+__device__ __forceinline__ void workgroup_min_store(double v, double* __restrict__ out) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v, off, 64);
+    v = (o < v) ? o : v;
+  }
+  __shared__ double red[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) r = (red[w] < r) ? red[w] : r;
+    *out = r;
+  }
+}
+
 // Cell of this thread when each workgroup of kBlock threads takes kBlock
 // consecutive cells in storage order (x fastest), so that no lane idles
 // whatever nx is (row tiles of 64 leave 8% of the lanes idle at nx = 352).
@@ -466,19 +500,26 @@ __device__ __forceinline__ bool linear_cell(const Geom& g, int& i, int& j, int& 
 // Primitive recovery for WENO-Z (FP64): every cell's primitives, in the order
 // of prim_at, into PW[8][n], so that the face kernel reads each of the six
 // cells of a stencil instead of recovering it again (each cell is in 18
-// stencils in 3D).
+// stencils in 3D). cflp != nullptr (3D): also the CFL bound of the state,
+// reduced over the workgroup into cflp[blockIdx.x]; k_cfl_final finishes it.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_prim_weno(const double* __restrict__ U,
                                                  double* __restrict__ PW, Geom g,
-                                                 int* __restrict__ flag) {
+                                                 int* __restrict__ flag,
+                                                 double* __restrict__ cflp) {
   int i, j, k;
   int64_t c;
-  if (!linear_cell(g, i, j, k, c)) return;
-  double V[8];
-  const bool ok = prim_at<DIM>(U, g, i, j, k, V);
+  const bool inside = linear_cell(g, i, j, k, c);
+  double cmin = __builtin_inf();
+  if (inside) {
+    double V[8];
+    const bool ok = prim_at<DIM>(U, g, i, j, k, V);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) PW[q * g.n + c] = V[q];
-  if (!ok) atomicOr(flag, 1);
+    for (int q = 0; q < 8; ++q) PW[q * g.n + c] = V[q];
+    if (!ok) atomicOr(flag, 1);
+    if (DIM == 3 && cflp) cmin = cfl_bound(g, V, cmin);
+  }
+  if (DIM == 3 && cflp) workgroup_min_store(cmin, cflp + blockIdx.x);
 }
 
 // Lower face of direction D of cell (i,j,k) with WENO-Z reconstruction (FP64)
@@ -603,20 +644,6 @@ __device__ __forceinline__ bool march_prim(const double* __restrict__ U, const G
 #pragma unroll
   for (int q = 0; q < 8; ++q) V[q] = (R)W[q];
   return ok;
-}
-
-// CFL bound of one cell from its FP64 primitives: min over directions of
-// dx_d / (|v_d| + c_f,d), the expression of k_cfl.
-__device__ __forceinline__ double cfl_bound(const Geom& g, const double* W, double m) {
-  const double dd[3] = {g.dx, g.dy, g.dz};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double cf = cfast<double>(g.gamma, W[0], W[4], W[5 + d], W[5 + (d + 1) % 3],
-                                    W[5 + (d + 2) % 3]);
-    const double t = dd[d] / (__builtin_fabs(W[1 + d]) + cf);
-    m = (t < m) ? t : m;
-  }
-  return m;
 }
 
 // Store a core cell's primitives: slots 0..6 in ring plane rp, B_z in bz
@@ -811,23 +838,7 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
       __syncthreads();
     }
   }
-  if (cflp) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double o = __shfl_xor(cmin, off, 64);
-      cmin = (o < cmin) ? o : cmin;
-    }
-    __shared__ double red[kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) red[wid] = cmin;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double r = red[0];
-#pragma unroll
-      for (int w = 1; w < kBlock / 64; ++w) r = (red[w] < r) ? red[w] : r;
-      cflp[blockIdx.x] = r;
-    }
-  }
+  if (cflp) workgroup_min_store(cmin, cflp + blockIdx.x);
   if (bad) atomicOr(flag, 1);
 }
 
@@ -920,11 +931,15 @@ hipError_t stage_impl(const StageArgs& a) {
   const unsigned nb = rg.ntiles;
   if constexpr (LIM == 2) {
     static_assert(sizeof(R) == 8, "WENO-Z runs in FP64");
-    if (a.cfl_partial || !a.PW) return hipErrorInvalidValue;  // the CFL is not fused here
+    if (!a.PW || (DIM == 2 && a.cfl_partial)) return hipErrorInvalidValue;
     const unsigned nl = (unsigned)((a.g.n + kBlock - 1) / kBlock);
     MHD_TIMED(a, K_PRIM,
               hipLaunchKernelGGL((k_prim_weno<DIM>), dim3(nl), dim3(kBlock), 0, a.stream, a.U,
-                                 a.PW, a.g, a.flag));
+                                 a.PW, a.g, a.flag, a.cfl_partial));
+    if (a.cfl_partial)  // dt of the state U, before the update kernel reads it
+      MHD_TIMED(a, K_CFL_FINAL,
+                hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, a.cfl_partial,
+                                   (int)nl, a.cfl, a.dt_out));
     MHD_TIMED(a, K_FACES,
               hipLaunchKernelGGL((k_faces_weno<DIM, RS>), dim3(nl), dim3(kBlock), 0, a.stream,
                                  a.PW, a.U, a.FW, a.g));
@@ -1009,7 +1024,9 @@ hipError_t stage_lim(const StageArgs& a) {
 
 }  // namespace
 
-size_t stage_cfl_blocks(const Geom& g) { return march_grid(g).nblocks; }
+size_t stage_cfl_blocks(const Geom& g, int limiter) {
+  return (limiter == 2) ? (size_t)((g.n + kBlock - 1) / kBlock) : march_grid(g).nblocks;
+}
 
 hipError_t launch_stage(const StageArgs& a) {
   return (a.dim == 3) ? stage_lim<3>(a) : stage_lim<2>(a);

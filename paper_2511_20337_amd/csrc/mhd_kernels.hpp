@@ -35,8 +35,9 @@ struct StageArgs {
   int* flag;              // sticky unphysical flag
   hipStream_t stream;
   Timer* timer;           // nullable
-  // 3D stage 1 only, optional: the face kernel also reduces the CFL bound of U
-  // into cfl_partial (stage_cfl_blocks(g) doubles), and *dt_out = cfl * min
+  // 3D stage 1 only, optional: the face kernel (with WENO-Z, the primitive
+  // kernel) also reduces the CFL bound of U
+  // into cfl_partial (stage_cfl_blocks(g, limiter) doubles), and *dt_out = cfl * min
   // is written before the update reads dtp (which then must be dt_out)
   double* cfl_partial;
   double cfl;
@@ -65,7 +66,7 @@ struct CflArgs {
 
 hipError_t launch_stage(const StageArgs& a);
 // number of CFL partials the 3D face kernel writes (one per workgroup)
-size_t stage_cfl_blocks(const Geom& g);
+size_t stage_cfl_blocks(const Geom& g, int limiter);
 hipError_t launch_cfl(const CflArgs& a);
 
 }  // namespace mhd
