@@ -148,7 +148,7 @@ __device__ __forceinline__ double wenoz_upper(double v0, double v1, double v2, d
   const double al0 = 0.1 * (beta0 + tau5) * (beta1 * beta2);
   const double al1 = 0.6 * (beta1 + tau5) * (beta0 * beta2);
   const double al2 = 0.3 * (beta2 + tau5) * (beta0 * beta1);
-  return __builtin_fma(al0, q0, __builtin_fma(al1, q1, al2 * q2)) / (6.0 * (al0 + al1 + al2));
+  return div_r(__builtin_fma(al0, q0, __builtin_fma(al1, q1, al2 * q2)), 6.0 * (al0 + al1 + al2));
 }
 
 // Face-frame primitive state: (rho, u_n, v_t1, v_t2, B_t1, B_t2, p).
