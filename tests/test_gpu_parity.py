@@ -187,6 +187,53 @@ def test_orszag_tang_3d_ten_step_parity(dev):
     assert (err <= 1e-12).all(), err
 
 
+def test_orszag_tang_3d_352_wenoz_rk3_sampled_parity(dev):
+    """The paper's 3D Orszag-Tang problem at its per-GPU size, 352^3, with the
+    paper's scheme (WENO-Z + SSP-RK3 + HLLD + CT) as the benchmark times it:
+    two steps of mhd_step_cfl against the separate CFL pass bit for bit, the
+    first dt against the oracle on the whole grid, the state after two steps
+    against the oracle at sampled cells (corners and random interior; two RK3
+    steps of the +-3-cell stencil reach 24 cells, the patches reach 26), then
+    conservation and div B on the whole grid."""
+    s, U0 = W.orszag_tang_3d(352, limiter="wenoz")
+    s = dict(s, integrator="rk3")
+    print("352^3 wenoz rk3: 2 steps, step_cfl against the separate pass", flush=True)
+    ctx = ctx_for(s, dev)
+    c = O.cfg_from(s)
+    U = torch.from_numpy(U0).to(dev)
+    Ub = U.clone()
+    dta = torch.zeros(1, dtype=torch.float64, device=dev)
+    dtb = torch.zeros(1, dtype=torch.float64, device=dev)
+    dts = []
+    for step in range(2):
+        ctx.dt_device(U, dta)
+        ctx.step_device_dt(U, dta)
+        ctx.step_cfl(Ub, dtb)
+        assert dta.item() == dtb.item(), step
+        assert torch.equal(U, Ub), step
+        dts.append(dtb.item())
+    del Ub
+    ctx.check()
+    assert dts[0] == pytest.approx(O.dt(c, U0), rel=1e-14)
+    print("352^3 wenoz rk3: sampled oracle patches", flush=True)
+    got = U.cpu().numpy()
+    rng = np.random.default_rng(21)
+    cen = [(0, 0, 0), (351, 351, 351), (0, 351, 176), (351, 0, 1)]
+    cen += [tuple(int(v) for v in rng.integers(0, 352, 3)) for _ in range(8)]
+    ref = oracle_at_samples(s, U0, dts, cen, radius=26)
+    g = np.array([got[:, k, j, i] for (k, j, i) in cen])
+    scale = np.abs(U0).max(axis=(1, 2, 3))
+    scale[5:8] = np.abs(U0[5:8]).max()  # B_z starts at zero: the field's scale
+    err = (np.abs(g - ref) / scale).max(axis=0)
+    assert (err <= 1e-12).all(), err
+    print("352^3 wenoz rk3: invariants", flush=True)
+    for q in range(8):
+        mag = np.abs(U0[q]).sum() if q < 5 else np.abs(U0[5:8]).sum()
+        assert abs(got[q].sum() - U0[q].sum()) <= 1e-12 * mag, q
+    div = O.divb(c, got)
+    assert np.abs(div).max() * (1 / 352) / np.abs(got[5:]).max() <= 1e-12
+
+
 def test_cp_alfven_3d_second_order_on_gpu(dev):
     """The paper's second benchmark problem, the 3D circularly polarised
     Alfven wave (k = 2 pi (1,1,1), eps = 0.1), an exact nonlinear solution: after
