@@ -138,8 +138,8 @@ mhd_status mhd_rhs(mhd_ctx* ctx, const double* U, double* L, void* ws, size_t ws
  * non-NULL, the host double *dtbar = (dPhi/d dt)^T Ubar_np1 (this one
  * synchronises). Not part of the paper: the derivative of every
  * non-smooth point (limiter at extrema, min/max, Riemann region switches) is
- * that of the branch the forward step takes. FP64, PLM and SSP-RK2 only
- * (MHD_ERR_UNSUPPORTED otherwise). Ubar_n must not
+ * that of the branch the forward step takes. FP64 and PLM, with either
+ * integrator (MHD_ERR_UNSUPPORTED otherwise). Ubar_n must not
  * alias Ubar_np1 or U_n. Needs mhd_workspace_bytes(ctx, 1). */
 mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const double* Ubar_np1,
                             double* Ubar_n, double* dtbar, void* ws, size_t ws_bytes,

@@ -1,9 +1,11 @@
-// Adjoint (vector-Jacobian product) of one SSP-RK2 step, FP64, gather form.
+// Adjoint (vector-Jacobian product) of one SSP-RK2 or SSP-RK3 step, FP64,
+// gather form.
 //
-// The step is Phi(Un) = (Un + S(S(Un)))/2 with S(U) = U + dt L(U). Reverse:
+// The RK2 step is Phi(Un) = (Un + S(S(Un)))/2 with S(U) = U + dt L(U). Reverse:
 //   G2 = Ubar1/2;        U1bar = G2 + dt J_L(U1)^T G2;
 //   Ubar0 = Ubar1/2 + U1bar + dt J_L(Un)^T U1bar;
 //   dtbar = <G2, L(U1)> + <U1bar, L(Un)>.
+// The RK3 step takes the same per-stage adjoint three times (adjoint_rk3).
 // J_L^T G is assembled from the local Jacobians of each piece of L, every
 // output written by exactly one thread (no atomics, deterministic):
 //   k_adj_edges — the EMF cotangent from -curl E, times the partial
@@ -413,7 +415,11 @@ struct Bufs {
   double* A;     // 8 x n: cotangent of the stage-1 state
   double* FWn;   // dim x NSLOT x n: face records at U_n (kept from the stage-1 forward)
   double* EWn;   // 3 x n: edge EMFs at U_n
-  double* part;  // 2 x nblocks: dtbar partial sums
+  // SSP-RK3 only (nullptr otherwise):
+  double* FW1;   // dim x NSLOT x n: face records at U1 (kept from the stage-2 forward)
+  double* EW1;   // 3 x n: edge EMFs at U1
+  double* A1;    // 8 x n: cotangent of the stage-1 state
+  double* part;  // (2 or 3) x nblocks: dtbar partial sums, one set per stage
 };
 
 template <int D>
@@ -757,7 +763,7 @@ __global__ __launch_bounds__(1024) void k_sum_final(const double* __restrict__ p
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-Bufs carve(double* scratch, int dim, int64_t n) {
+Bufs carve(double* scratch, int dim, int64_t n, int integrator) {
   Bufs b;
   double* p = scratch;
   b.EB = p; p += 3 * NE * n;
@@ -768,6 +774,12 @@ Bufs carve(double* scratch, int dim, int64_t n) {
   b.A = p; p += 8 * n;
   b.FWn = p; p += (int64_t)dim * NSLOT * n;
   b.EWn = p; p += 3 * n;
+  b.FW1 = b.EW1 = b.A1 = nullptr;
+  if (integrator == 1) {
+    b.FW1 = p; p += (int64_t)dim * NSLOT * n;
+    b.EW1 = p; p += 3 * n;
+    b.A1 = p; p += 8 * n;
+  }
   b.part = p;
   return b;
 }
@@ -789,10 +801,74 @@ hipError_t stage_adjoint(const AdjointArgs& a, const Bufs& bf, const double* U, 
   return hipGetLastError();
 }
 
+// Elementwise out = a x + b y (n doubles).
+__global__ __launch_bounds__(kBlock) void k_axpby(const double* __restrict__ x, double a,
+                                                  const double* __restrict__ y, double b,
+                                                  double* __restrict__ out, int64_t n) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c < n) out[c] = a * x[c] + b * y[c];
+}
+
+// Adjoint of one SSP-RK3 step (Eq. (RK3)): U1 = Un + dt L(Un),
+// U2 = 3/4 Un + 1/4 (U1 + dt L(U1)), U3 = 1/3 Un + 2/3 (U2 + dt L(U2)).
+// With G = Ubar of U3, in reverse:
+//   A2 = 2/3 (G + dt J(U2)^T G)        (cotangent of U2)
+//   A1 = 1/4 (A2 + dt J(U1)^T A2)      (cotangent of U1)
+//   Ubar_n = 3/4 A2 + 1/3 G + A1 + dt J(Un)^T A1,
+// and dtbar = sum over the stages of (s G_stage) . L(U_stage). The forward
+// pass keeps the face/edge records at Un and U1 and recomputes those at U2;
+// the direct term 3/4 A2 + 1/3 G goes to the space of U2, which nothing reads
+// after the last stage's adjoint.
+template <int DIM, int LIM, int RS>
+hipError_t adjoint_rk3(const AdjointArgs& a, const Bufs& bf, StageArgs f) {
+  const int64_t n = a.g.n;
+  const unsigned nb = blocks_for(n);
+  if (!a.U2 || !bf.FW1) return hipErrorInvalidValue;
+  f.stage = 1;  // U1 = Un + dt L(Un), records at Un kept
+  f.U = a.Un;
+  f.U0 = nullptr;
+  f.out = a.U1;
+  f.FW = bf.FWn;
+  f.EW = bf.EWn;
+  hipError_t e = launch_stage(f);
+  if (e != hipSuccess) return e;
+  f.stage = 4;  // U2 = (3 Un + (U1 + dt L(U1))) / 4, records at U1 kept
+  f.U = a.U1;
+  f.U0 = a.Un;
+  f.out = a.U2;
+  f.FW = bf.FW1;
+  f.EW = bf.EW1;
+  e = launch_stage(f);
+  if (e != hipSuccess) return e;
+  f.stage = 3;  // records at U2
+  f.U = a.U2;
+  f.U0 = nullptr;
+  f.FW = a.FW;
+  f.EW = a.EW;
+  e = launch_stage(f);
+  if (e != hipSuccess) return e;
+  e = stage_adjoint<DIM, LIM, RS>(a, bf, a.U2, a.FW, a.EW, a.Ubar1, 2.0 / 3.0, nullptr, 0.0, bf.A,
+                                  bf.part);
+  if (e != hipSuccess) return e;
+  const unsigned n8 = (unsigned)((8 * n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_axpby, dim3(n8), dim3(kBlock), 0, a.stream, bf.A, 0.75, a.Ubar1,
+                     1.0 / 3.0, a.U2, 8 * n);
+  e = stage_adjoint<DIM, LIM, RS>(a, bf, a.U1, bf.FW1, bf.EW1, bf.A, 0.25, nullptr, 0.0, bf.A1,
+                                  bf.part + nb);
+  if (e != hipSuccess) return e;
+  e = stage_adjoint<DIM, LIM, RS>(a, bf, a.Un, bf.FWn, bf.EWn, bf.A1, 1.0, a.U2, 1.0, a.Ubar0,
+                                  bf.part + 2 * nb);
+  if (e != hipSuccess) return e;
+  if (a.want_dtbar)
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(1024), 0, a.stream, bf.part, (int)(3 * nb),
+                       a.dtbar_dev);
+  return hipGetLastError();
+}
+
 template <int DIM, int LIM, int RS>
 hipError_t adjoint_impl(const AdjointArgs& a) {
   const int64_t n = a.g.n;
-  const Bufs bf = carve(a.scratch, a.dim, n);
+  const Bufs bf = carve(a.scratch, a.dim, n, a.integrator);
   const unsigned nb = blocks_for(n);
   StageArgs f{};
   f.dim = a.dim;
@@ -807,6 +883,7 @@ hipError_t adjoint_impl(const AdjointArgs& a) {
   f.flag = a.flag;
   f.stream = a.stream;
   f.timer = nullptr;
+  if (a.integrator == 1) return adjoint_rk3<DIM, LIM, RS>(a, bf, f);
   // forward stage 1: U1 = Un + dt L(Un); its face/edge records at Un are
   // kept (FWn, EWn) for the stage-1 adjoint
   f.stage = 1;
@@ -846,10 +923,11 @@ hipError_t adjoint_dim(const AdjointArgs& a) {
 
 }  // namespace
 
-size_t adjoint_workspace_bytes(int dim, size_t ncell) {
+size_t adjoint_workspace_bytes(int dim, size_t ncell, int integrator) {
   const size_t nb = (ncell + kBlock - 1) / kBlock;
-  const size_t per_cell = 3 * NE + 3 * 14 + 3 + 3 + 8 + 8 + (size_t)dim * NSLOT + 3;
-  return sizeof(double) * (per_cell * ncell + 2 * nb) + 256;
+  size_t per_cell = 3 * NE + 3 * 14 + 3 + 3 + 8 + 8 + (size_t)dim * NSLOT + 3;
+  if (integrator == 1) per_cell += (size_t)dim * NSLOT + 3 + 8;  // FW1, EW1, A1
+  return sizeof(double) * (per_cell * ncell + (integrator == 1 ? 3 : 2) * nb) + 256;
 }
 
 hipError_t launch_adjoint_step(const AdjointArgs& a) {

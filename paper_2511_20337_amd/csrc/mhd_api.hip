@@ -273,7 +273,7 @@ mhd_status mhd_init(const mhd_config* cfg, mhd_ctx** out) {
   if (cfg->limiter == MHD_LIM_WENOZ) off = align_up(off + sizeof(double) * 8 * n);
   c->bytes_fwd = off;
   c->off_adj = off;
-  c->bytes_adj = off + mhd::adjoint_workspace_bytes(cfg->dim, n);
+  c->bytes_adj = off + mhd::adjoint_workspace_bytes(cfg->dim, n, cfg->integrator);
   c->err[0] = '\0';
   *out = c;
   return MHD_OK;
@@ -364,20 +364,22 @@ static mhd_status adjoint_impl(mhd_ctx* ctx, const double* U_n, double dt, const
   if (!ctx) return MHD_ERR_INVALID;
   if (!U_n || !Ubar_np1 || !Ubar_n || !(dt > 0.0) || !std::isfinite(dt)) return MHD_ERR_INVALID;
   if (Ubar_n == Ubar_np1 || Ubar_n == U_n) return MHD_ERR_INVALID;
-  if (ctx->cfg.precision != MHD_PREC_FP64 || ctx->cfg.integrator != MHD_SSP_RK2 ||
-      ctx->cfg.limiter == MHD_LIM_WENOZ)
+  if (ctx->cfg.precision != MHD_PREC_FP64 || ctx->cfg.limiter == MHD_LIM_WENOZ)
     return MHD_ERR_UNSUPPORTED;
   if (!ws_ok(ctx, ws, ws_bytes, true)) return MHD_ERR_WORKSPACE;
   mhd::AdjointArgs a{};
   a.dim = ctx->cfg.dim;
   a.limiter = ctx->cfg.limiter;
   a.riemann = ctx->cfg.riemann;
+  a.integrator = ctx->cfg.integrator == MHD_SSP_RK3 ? 1 : 0;
   a.g = ctx->g;
   a.Un = U_n;
   a.Ubar1 = Ubar_np1;
   a.Ubar0 = Ubar_n;
   a.dt = dt;
   a.U1 = reinterpret_cast<double*>(base(ws) + ctx->off_u1);
+  a.U2 = ctx->cfg.integrator == MHD_SSP_RK3
+             ? reinterpret_cast<double*>(base(ws) + ctx->off_u2) : nullptr;
   a.FW = reinterpret_cast<double*>(base(ws) + ctx->off_fw);
   a.EW = reinterpret_cast<double*>(base(ws) + ctx->off_ew);
   a.scratch = reinterpret_cast<double*>(base(ws) + ctx->off_adj);

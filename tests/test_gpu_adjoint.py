@@ -69,6 +69,37 @@ def test_adjoint_elementwise(dev, dim, lim, solver):
     assert dtbar == pytest.approx(float((ubar * jdt).sum()), rel=1e-11, abs=1e-14)
 
 
+@pytest.mark.parametrize("case", ["2d_vanleer_hlld", "3d_vanleer_hlld", "3d_minmod_hll"])
+def test_adjoint_elementwise_rk3(dev, case):
+    """The adjoint of one SSP-RK3 step (the paper's integrator), element by
+    element against the oracle's tangent of its own RK3 step, and dt-bar."""
+    dim, lim, solver = case.split("_")
+    dim = int(dim[0])
+    if dim == 2:
+        s, U = smooth_ragged(2, 6, 5, 1, lim, solver)
+    else:
+        s, U = smooth_ragged(3, 5, 4, 4, lim, solver)
+    s = dict(s, integrator="rk3")
+    print("adjoint elementwise rk3", case, flush=True)
+    c = O.cfg_from(s)
+    dt = O.dt(c, U)
+    rng = np.random.default_rng(8)
+    ubar = rng.normal(size=U.shape)
+    got, dtbar = gpu_adjoint(s, U, dt, ubar, dev)
+    ref = np.zeros(U.size)
+    e = np.zeros(U.size)
+    for idx in range(U.size):
+        e[idx] = 1.0
+        _, jv = O.step_jvp(c, U, e.reshape(U.shape), dt)
+        ref[idx] = float((ubar * jv).sum())
+        e[idx] = 0.0
+    ref = ref.reshape(U.shape)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-11 * scale, np.abs(got - ref).max() / scale
+    _, jdt = O.step_jvp(c, U, np.zeros_like(U), dt, 1.0)
+    assert dtbar == pytest.approx(float((ubar * jdt).sum()), rel=1e-11, abs=1e-14)
+
+
 def _special_state(case):
     """Tie-free states that drive the Riemann solver into its other branches:
     supersonic faces both ways (HLLD early outs), a zero normal field on the
@@ -112,14 +143,16 @@ def test_adjoint_elementwise_special_states(dev, case, solver):
     assert dtbar == pytest.approx(float((ubar * jdt).sum()), rel=1e-11, abs=1e-14)
 
 
-@pytest.mark.parametrize("case", ["2d_32", "3d_12", "3d_16_minmod_hll"])
+@pytest.mark.parametrize("case", ["2d_32", "3d_12", "3d_16_minmod_hll", "3d_12_rk3", "2d_32_rk3"])
 def test_adjoint_dot_product(dev, case):
-    if case == "2d_32":
+    if case.startswith("2d_32"):
         s, U = smooth_ragged(2, 32, 28, 1, "vanleer", "hlld", seed=3)
-    elif case == "3d_12":
+    elif case.startswith("3d_12"):
         s, U = smooth_ragged(3, 12, 10, 11, "vanleer", "hlld", seed=4)
     else:
         s, U = smooth_ragged(3, 16, 16, 16, "minmod", "hll", seed=6)
+    if case.endswith("rk3"):
+        s = dict(s, integrator="rk3")
     c = O.cfg_from(s)
     dt = O.dt(c, U)
     rng = np.random.default_rng(11)
@@ -153,11 +186,10 @@ def test_adjoint_rejects_bad_arguments(dev):
     with pytest.raises(mhd.MHDError) as e:
         cm.adjoint_step(Ug, 1e-3, ub)
     assert e.value.status == mhd.MHD_ERR_UNSUPPORTED
-    for over in ({"integrator": "rk3"}, {"limiter": "wenoz"}):  # PLM + SSP-RK2 only
-        c3 = mhd.Context(dict(s, **over), dev, with_adjoint=True)
-        with pytest.raises(mhd.MHDError) as e:
-            c3.adjoint_step(Ug, 1e-3, ub)
-        assert e.value.status == mhd.MHD_ERR_UNSUPPORTED
+    c3 = mhd.Context(dict(s, limiter="wenoz"), dev, with_adjoint=True)  # PLM only
+    with pytest.raises(mhd.MHDError) as e:
+        c3.adjoint_step(Ug, 1e-3, ub)
+    assert e.value.status == mhd.MHD_ERR_UNSUPPORTED
 
 
 def test_multistep_gradient_checkpoint_invariant(dev):
