@@ -120,13 +120,14 @@ def _time_backward(AD, ctx, U0, dts, every):
     return n / (t2 - t1), n / (t1 - t0)
 
 
-def time_adjoint_blast(n, nsteps, every):
+def time_adjoint_blast(n, nsteps, every, integrator="rk2"):
     """Magnetised blast n^3 in FP64: N forward steps with checkpoints, then the
     checkpointed backward. Returns adjoint steps/s and forward steps/s."""
     import torch
     from paper_2511_20337_amd import adjoint as AD, mhd, workloads as W
     dev = torch.device("cuda:0")
     s, U = W.blast_3d(n, precision="fp64")
+    s = dict(s, integrator=integrator)
     ctx = mhd.Context(s, dev, with_adjoint=True)
     U0 = torch.from_numpy(U).to(dev)
     del U
@@ -189,9 +190,10 @@ def only_part(part, n, steps, warmup):
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
                "workload": "kelvin_helmholtz_2d_512"}
     else:
-        adj, fwd = time_adjoint_blast(256, 16, 4)
+        integ = "rk3" if part == "adjoint_3d_rk3" else "rk2"
+        adj, fwd = time_adjoint_blast(256, 16, 4, integ)
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
-               "workload": "blast_3d_256_fp64"}
+               "workload": "blast_3d_256_fp64 ssp_%s" % integ}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -210,7 +212,7 @@ def main(argv=None):
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters) and exit")
-    ap.add_argument("--only", choices=("mixed", "ot3d_wenoz", "adjoint", "adjoint_3d"), default=None,
+    ap.add_argument("--only", choices=("mixed", "ot3d_wenoz", "adjoint", "adjoint_3d", "adjoint_3d_rk3"), default=None,
                     help="run only this extra measurement and print it (for profiling)")
     args = ap.parse_args(argv)
     if args.copy_probe:
@@ -362,6 +364,10 @@ def main(argv=None):
                              "forward_steps_per_s": fwd3,
                              "config": {"workload": "blast_3d_256_fp64", "steps": 16,
                                         "checkpoint_every": 4}}
+        log("adjoint: the same with SSP-RK3")
+        adj3r, fwd3r = time_adjoint_blast(256, 16, 4, "rk3")
+        out["adjoint_3d"]["rk3"] = {"value": adj3r, "unit": "adjoint steps/s",
+                                    "forward_steps_per_s": fwd3r}
     if not args.no_cpu:
         log("cpu baseline: oracle at %d^3" % args.cpu_n)
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, make, args.cpu_steps)
