@@ -192,12 +192,14 @@ def test_adjoint_rejects_bad_arguments(dev):
     assert e.value.status == mhd.MHD_ERR_UNSUPPORTED
 
 
-def test_multistep_gradient_checkpoint_invariant(dev):
+@pytest.mark.parametrize("integrator", ["rk2", "rk3"])
+def test_multistep_gradient_checkpoint_invariant(dev, integrator):
     """Gradients of a 10-step run through the autograd wrapper: identical for
     checkpoint intervals 1, 3 and 10, and equal to a chain of oracle JVPs in
     the dot-product sense."""
     from paper_2511_20337_amd import adjoint as AD, mhd
     s, U = smooth_ragged(2, 16, 12, 1, "vanleer", "hlld", seed=5)
+    s = dict(s, integrator=integrator)
     ctx = mhd.Context(s, dev, with_adjoint=True)
     U0 = torch.from_numpy(U).to(dev)
     dts, _ = AD.record_dts(ctx, U0, 10)
