@@ -93,8 +93,8 @@ void mhd_destroy(mhd_ctx* ctx);
  * for mhd_adjoint_step as well). 256-byte alignment is required. */
 size_t mhd_workspace_bytes(const mhd_ctx* ctx, int32_t with_adjoint);
 
-/* Time step of the state U (CFL condition; the paper gives no formula, see
- * the design notes): dt = C min over cells and directions d of
+/* Time step of the state U (CFL condition; the paper gives no formula, so
+ * this is the usual one for ideal MHD): dt = C min over cells and directions d of
  * dx_d / (|v_d| + c_f,d), with c_f,d the fast magnetosonic speed along d.
  * Writes the host double *dt_out; synchronises the stream. Reports (and
  * clears) the unphysical flag as MHD_ERR_UNPHYSICAL, still writing dt. */

@@ -25,8 +25,8 @@
 //                                 paper cites for both benchmarks (Sec. 4.1, 4.2)
 //   constrained transport ....... Sec. 2.2 (CT keeps div B at machine precision)
 //
-// Every point where the paper is silent is taken with the reading listed in
-// the repository's design notes; each is marked [reading] below.
+// Every point where the paper is silent, ambiguous or garbled is taken with a
+// stated reading, marked [reading] below where it applies.
 //
 // All arithmetic is written with a scalar template parameter:
 //   S — scalar of the stored state, primitive recovery and accumulation;
