@@ -234,6 +234,43 @@ def test_orszag_tang_3d_352_wenoz_rk3_sampled_parity(dev):
     assert np.abs(div).max() * (1 / 352) / np.abs(got[5:]).max() <= 1e-12
 
 
+def _cp_alfven_gpu_error(dev, n, limiter, integrator):
+    """L1 error of B after one period of the 3D CP Alfven wave on the GPU."""
+    s, U0, period = W.cp_alfven(n, dim=3, cfl=0.3, limiter=limiter)
+    s = dict(s, integrator=integrator)
+    ctx = ctx_for(s, dev)
+    U = torch.from_numpy(U0).to(dev)
+    nsteps = int(math.ceil(period / ctx.dt(U)))
+    for _ in range(nsteps):
+        ctx.step(U, period / nsteps)
+    ctx.check()
+    return float(np.mean(np.abs(U.cpu().numpy()[5:8] - U0[5:8]))), s, U0, period, nsteps
+
+
+def test_cp_alfven_3d_paper_scheme_on_gpu(dev):
+    """The paper's scheme (WENO-Z + SSP-RK3 + HLLD + CT) on its second
+    benchmark problem, the 3D circularly polarised Alfven wave: after one
+    period the L1 error of B at 32^3 is the oracle's; from 64^3 to 256^3 it
+    falls at order >= 1.8 (the CT edge values are PLM, so the scheme is second
+    order overall) and stays below 0.6 of PLM + SSP-RK2's at every size (the
+    oracle: 0.55 at 16^3, 0.52 at 32^3)."""
+    e32, s, U0, period, nsteps = _cp_alfven_gpu_error(dev, 32, "wenoz", "rk3")
+    ref = O.run_dts(O.cfg_from(s), U0, [period / nsteps] * nsteps)
+    e_ref = float(np.mean(np.abs(ref[5:8] - U0[5:8])))
+    print("cp-alfven wenoz rk3 32", e32, e_ref, flush=True)
+    assert e32 == pytest.approx(e_ref, rel=1e-9)
+    errs = []
+    for n in (64, 128, 256):
+        ew = _cp_alfven_gpu_error(dev, n, "wenoz", "rk3")[0]
+        ep = _cp_alfven_gpu_error(dev, n, "vanleer", "rk2")[0]
+        print("cp-alfven", n, "wenoz+rk3", ew, "vanleer+rk2", ep, flush=True)
+        assert ew <= 0.6 * ep, (n, ew, ep)
+        errs.append(ew)
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    print("cp-alfven wenoz rk3 orders", orders, flush=True)
+    assert min(orders) >= 1.8, orders
+
+
 def test_cp_alfven_3d_second_order_on_gpu(dev):
     """The paper's second benchmark problem, the 3D circularly polarised
     Alfven wave (k = 2 pi (1,1,1), eps = 0.1), an exact nonlinear solution: after
