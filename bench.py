@@ -32,8 +32,12 @@ METRIC = ("Mcell-updates/s at 256³ (FP64 vs mixed FP32/FP64) + % HBM roofline; 
           "adjoint step/s")
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    """Progress line on stderr, prefixed with the seconds since start."""
+    print("[%6.1f s]" % (time.perf_counter() - _T0), *a, file=sys.stderr, flush=True)
 
 
 # Algorithmic work of one launch of each forward kernel, per cell (3D):
