@@ -58,3 +58,21 @@ def test_strerror_texts():
     assert mhd.strerror(0) == "ok"
     assert "unphysical" in mhd.strerror(-4)
     assert "workspace" in mhd.strerror(-5)
+
+
+def test_c_abi_program_rejects_bad_input_without_a_gpu(tmp_path):
+    """The host program built on the bare C ABI (tests/c_abi) stops with a
+    usage error for a wrong argument count and with mhd_init's status for an
+    invalid configuration, both before any device call."""
+    import subprocess
+    exe = os.path.join(ROOT, "tests", "c_abi", "step_cli")
+    assert os.path.exists(exe), "tests/c_abi/step_cli is missing: run __graft_entry__.build()"
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage" in r.stderr
+    fin = tmp_path / "in.bin"
+    fin.write_bytes(b"")
+    bad = ["4", "8", "8", "8", "0", "1", "0", "1", "0", "1", "1.6666666666666667", "0.3",
+           "1", "0", "0", "0"]  # dim 4
+    r = subprocess.run([exe, str(fin), str(tmp_path / "out.bin"), "1"] + bad,
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "mhd_init" in r.stderr, r.stderr
