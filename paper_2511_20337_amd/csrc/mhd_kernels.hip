@@ -487,7 +487,18 @@ __device__ __forceinline__ void workgroup_min_store(double v, double* __restrict
 // whatever nx is (row tiles of 64 leave 8% of the lanes idle at nx = 352).
 // The configuration check keeps n below 2^32.
 __device__ __forceinline__ bool linear_cell(const Geom& g, int& i, int& j, int& k, int64_t& c) {
-  const uint32_t t = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
+  // Workgroups are dealt round-robin to the 8 XCDs. Within each full group of
+  // 512, XCD x takes the 64 consecutive blocks x*64 .. x*64+63, so that rows
+  // three above and below a cell are mostly in the same XCD's L2; the groups
+  // themselves still advance together through the planes.
+  const uint32_t nb = (uint32_t)((g.n + kBlock - 1) / kBlock);
+  uint32_t blk = blockIdx.x;
+  const uint32_t grp = blk / 512u;
+  if ((grp + 1u) * 512u <= nb) {
+    const uint32_t w = blk % 512u;
+    blk = grp * 512u + (w % 8u) * 64u + w / 8u;
+  }
+  const uint32_t t = blk * (uint32_t)kBlock + threadIdx.x;
   if ((int64_t)t >= g.n) return false;
   const uint32_t r = t / (uint32_t)g.nx;
   i = (int)(t - r * (uint32_t)g.nx);
