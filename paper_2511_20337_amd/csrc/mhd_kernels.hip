@@ -89,6 +89,21 @@ __device__ __forceinline__ void tile_origin(const TileGrid& tg, unsigned t, int&
   k0 = tz * T::TZ;
 }
 
+// Workgroup order of the WENO-Z kernels: the hardware deals workgroups
+// round-robin to the 8 XCDs, each with its own L2. Within every full group of
+// 512 workgroups, XCD x is given the 64 consecutive ones x*64 .. x*64+63, so
+// that neighbouring rows (the stencil's reach along y) are mostly read through
+// the same L2, while all XCDs still advance together through the domain and
+// share the Infinity Cache. A permutation of 0 .. nb-1; a last partial group
+// keeps its order. (Measured slower for the z-marching face kernel, whose
+// neighbouring columns share the Infinity Cache better round-robin.)
+__device__ __forceinline__ unsigned xcd_grouped(unsigned b, unsigned nb) {
+  const unsigned grp = b / 512u;
+  if ((grp + 1u) * 512u > nb) return b;
+  const unsigned w = b % 512u;
+  return grp * 512u + (w % 8u) * 64u + w / 8u;
+}
+
 // Cell of this thread in the row-tile traversal; false outside the domain.
 __device__ __forceinline__ bool row_cell(const Geom& g, const TileGrid& tg, int& i, int& j, int& k) {
   const unsigned t = blockIdx.x;
@@ -483,22 +498,12 @@ __device__ __forceinline__ void workgroup_min_store(double v, double* __restrict
 }
 
 // Cell of this thread when each workgroup of kBlock threads takes kBlock
-// consecutive cells in storage order (x fastest), so that no lane idles
+// consecutive cells in storage order (x fastest; workgroups in the
+// XCD-grouped order of xcd_grouped), so that no lane idles
 // whatever nx is (row tiles of 64 leave 8% of the lanes idle at nx = 352).
 // The configuration check keeps n below 2^32.
 __device__ __forceinline__ bool linear_cell(const Geom& g, int& i, int& j, int& k, int64_t& c) {
-  // Workgroups are dealt round-robin to the 8 XCDs. Within each full group of
-  // 512, XCD x takes the 64 consecutive blocks x*64 .. x*64+63, so that rows
-  // three above and below a cell are mostly in the same XCD's L2; the groups
-  // themselves still advance together through the planes.
-  const uint32_t nb = (uint32_t)((g.n + kBlock - 1) / kBlock);
-  uint32_t blk = blockIdx.x;
-  const uint32_t grp = blk / 512u;
-  if ((grp + 1u) * 512u <= nb) {
-    const uint32_t w = blk % 512u;
-    blk = grp * 512u + (w % 8u) * 64u + w / 8u;
-  }
-  const uint32_t t = blk * (uint32_t)kBlock + threadIdx.x;
+  const uint32_t t = xcd_grouped(blockIdx.x, gridDim.x) * (uint32_t)kBlock + threadIdx.x;
   if ((int64_t)t >= g.n) return false;
   const uint32_t r = t / (uint32_t)g.nx;
   i = (int)(t - r * (uint32_t)g.nx);
