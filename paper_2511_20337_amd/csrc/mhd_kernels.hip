@@ -89,7 +89,8 @@ __device__ __forceinline__ void tile_origin(const TileGrid& tg, unsigned t, int&
   k0 = tz * T::TZ;
 }
 
-// Workgroup order of the WENO-Z kernels: the hardware deals workgroups
+// Workgroup order of the WENO-Z kernels (and of the mixed-mode EMF and update
+// kernels): the hardware deals workgroups
 // round-robin to the 8 XCDs, each with its own L2. Within every full group of
 // 512 workgroups, XCD x is given the 64 consecutive ones x*64 .. x*64+63, so
 // that neighbouring rows (the stencil's reach along y) are mostly read through
@@ -105,8 +106,10 @@ __device__ __forceinline__ unsigned xcd_grouped(unsigned b, unsigned nb) {
 }
 
 // Cell of this thread in the row-tile traversal; false outside the domain.
+// XG: workgroups in the XCD-grouped order (xcd_grouped) instead of round-robin.
+template <bool XG = false>
 __device__ __forceinline__ bool row_cell(const Geom& g, const TileGrid& tg, int& i, int& j, int& k) {
-  const unsigned t = blockIdx.x;
+  const unsigned t = XG ? xcd_grouped(blockIdx.x, gridDim.x) : blockIdx.x;
   const int tx = (int)(t % (unsigned)tg.ntx);
   const unsigned r = t / (unsigned)tg.ntx;
   const int ty = (int)(r % (unsigned)tg.nty);
@@ -177,7 +180,8 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
                                                       const double* __restrict__ FW,
                                                       double* __restrict__ EW, Geom g,
                                                       MarchGrid mg) {
-  const unsigned b = blockIdx.x;
+  // mixed mode: the XCD-grouped order (0.523 -> 0.513 ms at 256^3; FP64 unchanged)
+  const unsigned b = (sizeof(R) == 4) ? xcd_grouped(blockIdx.x, gridDim.x) : blockIdx.x;
   const int tx = (int)(b % (unsigned)mg.ntx);
   const unsigned r = b / (unsigned)mg.ntx;
   const int ty = (int)(r % (unsigned)mg.nty);
@@ -301,7 +305,9 @@ __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict
                                                    TileGrid tg, double dt,
                                                    const double* __restrict__ dtp) {
   int i, j, k;
-  if (!row_cell(g, tg, i, j, k)) return;
+  // mixed mode (FP32 records): the XCD-grouped order, measured faster there
+  // (0.777 -> 0.738 ms at 256^3) and slower in FP64
+  if (!row_cell<sizeof(R) == 4>(g, tg, i, j, k)) return;
   const int64_t c = lin(g, i, j, k);
   const int64_t n = g.n;
   const double h = (STAGE == 0) ? 0.0 : (dtp ? *dtp : dt);
