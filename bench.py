@@ -58,6 +58,12 @@ KERNEL_TRAFFIC = {"faces": 202.4 + 216.0}
 # FP32; it is bound by HBM (see profiles/), so its roofline entry is in bytes.
 KERNEL_BYTES_MIXED = {"faces": 8 * 8 + 4 * 27}
 KERNEL_TRAFFIC_MIXED = {"faces": 203.0 + 108.0}
+# WENO-Z face kernel on the 3D Orszag-Tang problem (FP64, HLLD): algorithmic
+# flops per cell of the oracle's face phase on that workload at 64^3 (count_flops.py;
+# its textbook WENO-Z with seven divisions per value, each one flop), and the
+# HBM bytes per cell counted at 352^3 (reads past L2 x2.0, writes x1.0).
+WENO_FACE_FLOPS = 4039.2
+WENO_FACE_TRAFFIC = 380.6 + 216.0
 
 
 def time_gpu(setup, U0, steps, warmup, timing=True):
@@ -173,6 +179,17 @@ def copy_probe(mib: int) -> int:
     return 0
 
 
+def weno_roofline(kt, ncell):
+    """ALU roofline entry of the WENO-Z face kernel from its event times."""
+    tot_ms, launches = kt["faces"]
+    avg_s = tot_ms / launches / 1e3
+    achieved = WENO_FACE_FLOPS * ncell / avg_s
+    return {"kernel": "faces", "bound": "alu", "achieved": achieved / 1e12,
+            "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
+            "traffic": WENO_FACE_TRAFFIC * ncell, "traffic_unit": "bytes per launch",
+            "avg_launch_ms": avg_s * 1e3, "flops_per_cell": WENO_FACE_FLOPS}
+
+
 def only_part(part, n, steps, warmup):
     """One extra measurement alone, printed as one JSON line."""
     from paper_2511_20337_amd import workloads as W
@@ -188,7 +205,8 @@ def only_part(part, n, steps, warmup):
         out = {"part": part, "value": n ** 3 * steps / el / 1e6, "unit": "Mcell-updates/s",
                "workload": "orszag_tang_3d_%d wenoz ssp_rk3 hlld" % n, "physical": phys,
                "ms_per_step": el / steps * 1e3,
-               "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]}}
+               "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]},
+               "roofline": weno_roofline(kt, n ** 3)}
     elif part == "adjoint":
         adj, fwd = time_adjoint(512, 64, 8)
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
@@ -356,7 +374,8 @@ def main(argv=None):
         out["orszag_tang_3d"]["wenoz_rk3"] = {
             "value": 352 ** 3 * steps_o / el_ow / 1e6, "unit": "Mcell-updates/s",
             "ms_per_step": el_ow / steps_o * 1e3, "physical": phys_ow,
-            "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_ow.items() if v[1]}}
+            "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_ow.items() if v[1]},
+            "roofline": weno_roofline(kt_ow, 352 ** 3)}
         log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, checkpoints every 8")
         adj, fwd = time_adjoint(512, 64, 8)
         out["adjoint"] = {"value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
