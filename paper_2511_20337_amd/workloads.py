@@ -468,3 +468,26 @@ WORKLOADS = {
     "kelvin_helmholtz_2d": kelvin_helmholtz_2d,
     "blast_3d": blast_3d,
 }
+
+
+def aligned_field_bump(dim=3, nx=24, ny=8, nz=8, axes=(0, 1, 2), limiter="vanleer",
+                       riemann="hlld", cfl=0.3, B0=1.0, p0=0.1):
+    """Uniform plasma in a uniform field B = (B0, 0, 0) whose Alfven speed
+    exceeds the sound speed (rho = 1, p = p0), with v = (0.3, -0.2, 0.1), and a
+    smooth compact bump in rho, p and v_y around the box centre that varies
+    only along `axes`. Outside the bump the state is exactly uniform, so the
+    x-faces there see identical states with B_t = 0, where the HLLD star state
+    is degenerate (rho (S-u)(S-S_M) = B_n^2)."""
+    nz = nz if dim == 3 else 1
+    s = make_setup("aligned_field_bump", dim, nx, ny, nz, (0, 1, 0, 1, 0, 1), 5.0 / 3.0, cfl,
+                   limiter, riemann)
+    x, y, z = centres(s)
+    r2 = np.zeros((nz, ny, nx))
+    for ax, c in ((0, x), (1, y), (2, z)):
+        if ax in axes and (ax < 2 or dim == 3):
+            r2 = r2 + ((c - 0.5) / 0.22) ** 2
+    bump = np.where(r2 < 1.0, np.cos(0.5 * np.pi * np.sqrt(np.minimum(r2, 1.0))) ** 2, 0.0)
+    rho = 1.0 + 0.3 * bump
+    p = p0 * (1.0 + 0.5 * bump)
+    vy = -0.2 + 0.2 * bump
+    return s, assemble(s, rho, 0.3, vy, 0.1, p, B0, 0.0, 0.0)

@@ -103,8 +103,14 @@ def test_adjoint_elementwise_rk3(dev, case):
 def _special_state(case):
     """Tie-free states that drive the Riemann solver into its other branches:
     supersonic faces both ways (HLLD early outs), a zero normal field on the
-    z-faces (sign(0), no Alfven fan), and a fluid at rest (min/max of equal
-    normal velocities)."""
+    z-faces (sign(0), no Alfven fan), a fluid at rest (min/max of equal
+    normal velocities), and degenerate HLLD star states (B_t = 0 with the
+    Alfven speed above the sound speed, identical states on both sides)."""
+    if case == "bt_zero_uniform":
+        # field along x, Alfven speed above sound speed, a bump varying along x
+        # in an exactly uniform state: degenerate HLLD star states on the
+        # x-faces outside the bump, plane-parallel (exact ties) across y and z
+        return W.aligned_field_bump(3, 8, 4, 4, axes=(0,))
     s, U = W.generic_state(3, 5, 4, 4, "vanleer", "hlld", seed=1)
     V = O.prim(O.cfg_from(s), U)
     bx, by, bz = U[5].copy(), U[6].copy(), U[7].copy()
@@ -119,7 +125,8 @@ def _special_state(case):
     return s, W.assemble(s, V[0], V[1], V[2], V[3], V[4], bx, by, bz)
 
 
-@pytest.mark.parametrize("case", ["supersonic_up", "supersonic_down", "bz_zero", "at_rest"])
+@pytest.mark.parametrize("case", ["supersonic_up", "supersonic_down", "bz_zero", "at_rest",
+                                  "bt_zero_uniform"])
 @pytest.mark.parametrize("solver", ["hlld", "hll"])
 def test_adjoint_elementwise_special_states(dev, case, solver):
     s, U = _special_state(case)

@@ -102,6 +102,24 @@ def test_rhs_parity_fp64(dev, dim, lim, solver):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("solver", ["hlld", "hll"])
+@pytest.mark.parametrize("lim", ["minmod", "vanleer"])
+def test_rhs_parity_degenerate_star_states(dev, dim, solver, lim):
+    """A field along x only (B_t = 0 on x-faces), Alfven speed above sound
+    speed, and a compact bump in an otherwise exactly uniform state: the
+    x-faces outside the bump see identical states with rho (S-u)(S-S_M) equal
+    to B_n^2 up to rounding, where HLLD takes its degenerate branch."""
+    s, U = W.aligned_field_bump(dim, 24, 16, 8, limiter=lim, riemann=solver)
+    print("rhs parity, degenerate star states", dim, lim, solver, flush=True)
+    ctx = ctx_for(s, dev)
+    got = ctx.rhs(torch.from_numpy(U).to(dev)).cpu().numpy()
+    ref = O.rhs(O.cfg_from(s), U)
+    assert np.isfinite(got).all()
+    err = rel_err(got, ref)
+    assert (err <= 1e-12).all(), err
+
+
+@pytest.mark.parametrize("dim", [2, 3])
 def test_dt_parity(dev, dim):
     s, U = ragged(dim, "vanleer", "hlld")
     ctx = ctx_for(s, dev)

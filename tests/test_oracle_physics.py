@@ -159,6 +159,14 @@ def test_linear_alfven_wave_minmod_order():
     assert math.log2(e[0] / e[1]) >= 1.3, e
 
 
+def test_linear_alfven_wave_vanleer_second_order():
+    """The smooth linear wave (amplitude 1e-6) with van Leer: second order
+    (measured 1.81 from 32^2 to 64^2 and 1.95 from 64^2 to 128^2)."""
+    e = [_cpa_error(n, 2, eps=1e-6, lim="vanleer") for n in (32, 64, 128)]
+    o1, o2 = math.log2(e[0] / e[1]), math.log2(e[1] / e[2])
+    assert o1 >= 1.75 and o2 >= 1.9, (e, o1, o2)
+
+
 # --------------------------------------------------------- invariants ------
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("solver", ["hlld", "hll"])

@@ -299,3 +299,209 @@ def test_wenoz_pins():
     orders = [math.log2(errs[q] / errs[q + 1]) for q in range(3)]
     assert min(orders) >= 4.9, (errs, orders)
 
+
+
+# ------------------------------------------ HLLD degenerate star states ----
+DEG_TOL = 1e-12  # the oracle's relative tolerance of the degeneracy test (FP64)
+
+
+def _degenerate_side(w, S, SM, bn):
+    """Whether the degeneracy test of the HLLD star state of one side holds:
+    D = rho (S - u)(S - S_M) - B_n^2 within DEG_TOL of its terms. Evaluated
+    here in the order the method states, from the wave speeds below."""
+    big = w[0] * (S - w[1]) * (S - SM)
+    return abs(big - bn * bn) <= DEG_TOL * (abs(big) + bn * bn)
+
+
+def _speeds(wl, wr, bn, g=G53):
+    cl = O.fast_speed(g, wl[0], wl[6], bn, wl[4], wl[5])
+    cr = O.fast_speed(g, wr[0], wr[6], bn, wr[4], wr[5])
+    SL = min(wl[1], wr[1]) - max(cl, cr)
+    SR = max(wl[1], wr[1]) + max(cl, cr)
+    ptl = wl[6] + 0.5 * (bn * bn + wl[4] ** 2 + wl[5] ** 2)
+    ptr = wr[6] + 0.5 * (bn * bn + wr[4] ** 2 + wr[5] ** 2)
+    ml, mr = (SL - wl[1]) * wl[0], (SR - wr[1]) * wr[0]
+    SM = (mr * wr[1] - ml * wl[1] - ptr + ptl) / (mr - ml)
+    return SL, SR, SM
+
+
+def test_hlld_degenerate_branch_consistency():
+    """Identical states with B_t = 0 and an Alfven speed above the sound speed:
+    c_f = |B_n| / sqrt(rho), so D = rho c_f^2 - B_n^2 vanishes up to rounding
+    and both star states take the degenerate branch (checked by recomputing D).
+    The flux must still be the physical flux F(U) (consistency); the
+    non-degenerate formula would divide B_t = 0 by D ~ 0 there."""
+    rng = np.random.default_rng(21)
+    hits = 0
+    for _ in range(200):
+        rho = rng.uniform(0.3, 3.0)
+        bn = rng.choice([-1.0, 1.0]) * rng.uniform(0.5, 3.0)
+        # sound speed well below the Alfven speed: gamma p < B_n^2 / 2
+        p = rng.uniform(0.01, 0.45) * bn * bn / G53
+        w = np.array([rho, rng.normal(), rng.normal(), rng.normal(), 0.0, 0.0, p])
+        SL, SR, SM = _speeds(w, w, bn)
+        assert SM == pytest.approx(w[1], rel=1e-12, abs=1e-14)
+        degl, degr = _degenerate_side(w, SL, SM, bn), _degenerate_side(w, SR, SM, bn)
+        hits += degl and degr
+        out = O.riemann(w, w, bn, solver="hlld")
+        assert np.isfinite(out).all()
+        np.testing.assert_allclose(out[:7], O.flux(w, bn)[1], rtol=1e-13, atol=1e-13)
+    assert hits >= 150, hits  # the branch is reached, not skipped
+
+
+def _three_wave_bn(wl, wr, bn, g=G53):
+    """Three-wave (HLLC-type) flux of ideal MHD when both states carry B_t = 0
+    and equal transverse velocities: the Euler HLLC flux of Toro's book with
+    the MHD bounds S_L, S_R (c_f = max(c_s, |B_n|/sqrt(rho))), plus the constant
+    normal field: -B_n^2/2 in the normal momentum flux, -v_t B_n in the
+    transverse field fluxes, and B_n^2/2 added to every energy (which leaves
+    the energy flux, (E_gas + p) u, unchanged)."""
+    def euler(w):
+        rho, u, v, ww, _, _, p = w
+        E = p / (g - 1) + 0.5 * rho * (u * u + v * v + ww * ww)
+        return (np.array([rho, rho * u, rho * v, rho * ww, E]),
+                np.array([rho * u, rho * u * u + p, rho * u * v, rho * u * ww, (E + p) * u]))
+    UL, FL = euler(wl)
+    UR, FR = euler(wr)
+    cfl = max(math.sqrt(g * wl[6] / wl[0]), abs(bn) / math.sqrt(wl[0]))
+    cfr = max(math.sqrt(g * wr[6] / wr[0]), abs(bn) / math.sqrt(wr[0]))
+    SL = min(wl[1], wr[1]) - max(cfl, cfr)
+    SR = max(wl[1], wr[1]) + max(cfl, cfr)
+    if SL > 0:
+        F = FL
+    elif SR < 0:
+        F = FR
+    else:
+        SM = (wr[6] - wl[6] + wl[0] * wl[1] * (SL - wl[1]) - wr[0] * wr[1] * (SR - wr[1])) / \
+            (wl[0] * (SL - wl[1]) - wr[0] * (SR - wr[1]))
+
+        def star(w, U, S):
+            rho, u, v, ww, _, _, p = w
+            f = rho * (S - u) / (S - SM)
+            return np.array([f, f * SM, f * v, f * ww,
+                             f * (U[4] / rho + (SM - u) * (SM + p / (rho * (S - u))))])
+        F = FL + SL * (star(wl, UL, SL) - UL) if SM >= 0 else FR + SR * (star(wr, UR, SR) - UR)
+    v, ww = wl[2], wl[3]
+    return np.array([F[0], F[1] - 0.5 * bn * bn, F[2], F[3], -v * bn, -ww * bn, F[4]])
+
+
+def test_hlld_without_transverse_field_is_three_wave_flux():
+    """B_t = 0 on both sides and equal transverse velocities: no rotational
+    wave carries anything, so HLLD is the three-wave flux with the same S_L,
+    S_M, S_R (written out independently above). Random L != R states, and
+    near-identical states (relative jumps of 1e-14) for which the degenerate
+    branch fires on one or both sides with L != R (counted)."""
+    rng = np.random.default_rng(22)
+    deg = 0
+    for trial in range(600):
+        bn = rng.normal() * (2.0 if trial % 2 else 0.5)
+        v, ww = rng.normal(), rng.normal()
+        wl = np.array([rng.uniform(0.3, 2.0), rng.normal(), v, ww, 0.0, 0.0,
+                       rng.uniform(0.02, 2.0)])
+        if trial < 300:
+            wr = np.array([rng.uniform(0.3, 2.0), rng.normal(), v, ww, 0.0, 0.0,
+                           rng.uniform(0.02, 2.0)])
+        else:
+            wl[6] = rng.uniform(0.01, 0.4) * bn * bn / G53  # Alfven speed above sound speed
+            wr = wl * (1.0 + 1e-14 * rng.uniform(-1, 1, 7))
+            wr[4:6] = 0.0
+            wr[2:4] = (v, ww)
+        SL, SR, SM = _speeds(wl, wr, bn)
+        if SL < 0 < SR:
+            deg += _degenerate_side(wl, SL, SM, bn) or _degenerate_side(wr, SR, SM, bn)
+        out = O.riemann(wl, wr, bn, solver="hlld")
+        want = _three_wave_bn(wl, wr, bn)
+        np.testing.assert_allclose(out[:7], want, rtol=1e-11, atol=1e-12 * (1 + bn * bn))
+    assert deg >= 100, deg
+
+
+# ----------------------------------------------------- operation counter --
+def _hand_count_uniform(dim, solver):
+    """Floating-point operations per cell of one right-hand side on a uniform
+    state at rest with every field component nonzero (every limiter at an
+    extremum, every face in the same Riemann region), counted by hand from
+    the method's formulas as the oracle writes them: (add/sub, mul, div,
+    sqrt) per phase. Unary minus, comparisons, min/max and abs are free."""
+    def tot(*parts):
+        return tuple(sum(p[k] for p in parts) for k in range(4))
+
+    def times(p, m):
+        return tuple(m * x for x in p)
+    # primitives: B_c = (b + b+)/2 per direction [(1, 1) each; 2D: B_z given],
+    # v = m/rho (3 div), kin = (m.v)/2 (2 add 4 mul), mag = |B|^2/2 (2 add 4 mul),
+    # p = (gamma - 1)(E - kin - mag) (3 add 1 mul)
+    prims = tot(times((1, 1, 0, 0), dim), (0, 0, 3, 0), (2, 4, 0, 0), (2, 4, 0, 0), (3, 1, 0, 0))
+    # PLM of one quantity at a face: two differences and dm*dp (zero product
+    # at an extremum: slope 0), then b + slope/2: 2 add + 1 mul + (1 add 1 mul);
+    # both sides, seven quantities
+    plm = times((3, 2, 0, 0), 2 * 7)
+    # physical state of one side: B^2 (2 add 3 mul), v^2 (2, 3), p_T (1, 1),
+    # E (3 add 3 mul 1 div), momenta (0, 3), v.B (2, 3), fluxes:
+    # rho u (0, 1), rho u u + p_T - Bn Bn (2, 3), two transverse momenta (1, 3)
+    # each, two induction fluxes (1, 2) each, energy (2, 2)
+    side = tot((2, 3, 0, 0), (2, 3, 0, 0), (1, 1, 0, 0), (3, 3, 1, 0), (0, 3, 0, 0),
+               (2, 3, 0, 0), (0, 1, 0, 0), (2, 3, 0, 0), (1, 3, 0, 0), (1, 3, 0, 0),
+               (1, 2, 0, 0), (1, 2, 0, 0), (2, 2, 0, 0))
+    # fast speed of one side: gamma p (0, 1), B^2 (2, 3), a (1, 0),
+    # a^2 - 4 gamma p Bn^2 (1, 4), sqrt, (a + sqrt) (1, 0), 2 rho (0, 1), div, sqrt
+    fast = tot((0, 1, 0, 0), (2, 3, 0, 0), (1, 0, 0, 0), (1, 4, 0, 1), (1, 0, 0, 0),
+               (0, 1, 1, 1))
+    # S_L, S_R (2 add); two weighted velocities (2 add 2 mul 1 div each)
+    common = tot(times(side, 2), times(fast, 2), (2, 0, 0, 0), (4, 4, 2, 0))
+    if solver == "hll":
+        # fan: (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L), 7 components
+        rs = times((4, 4, 1, 0), 7)
+    else:
+        # HLLD at rest (S_M = 0, region F**_L): S - u both sides (2 add);
+        # denominator (1 add 2 mul); S_M (3 add 4 mul 1 div); p_T* (3 add 8 mul 1 div)
+        head = tot((2, 0, 0, 0), (1, 2, 0, 0), (3, 4, 1, 0), (3, 8, 1, 0))
+        # one star side: S - u, S - S_M (2 add); rho* (1 mul 1 div); rho(S-u)(S-S_M)
+        # (2 mul); D (1 add 1 mul); degeneracy test (1 add 2 mul); factor of v*
+        # (1 add 1 mul 1 div); v*, w* (1 add 1 mul each); factor of B* (1 add 3 mul
+        # 1 div); B*_t (2 mul); v.B, v*.B* (2 add 3 mul each); E* (4 add 4 mul
+        # 1 div); star momenta (3 mul)
+        star = tot((2, 0, 0, 0), (0, 1, 1, 0), (0, 2, 0, 0), (1, 1, 0, 0), (1, 2, 0, 0),
+                   (1, 1, 1, 0), (2, 2, 0, 0), (1, 3, 1, 0), (0, 2, 0, 0), (4, 6, 0, 0),
+                   (4, 4, 1, 0), (0, 3, 0, 0))
+        # Alfven fronts: two sqrt, S*_L and S*_R (1 add 1 div each),
+        # 1/(s_L + s_R) (1 add 1 div); v**, w** (3 add 4 mul each); B**_t1, B**_t2
+        # (3 add 6 mul each); v**.B** (1 add 2 mul); E**_L and E**_R (3 add 4 mul each)
+        alf = tot((0, 0, 0, 2), (2, 0, 2, 0), (1, 0, 1, 0), (6, 8, 0, 0), (6, 12, 0, 0),
+                  (1, 2, 0, 0), (6, 8, 0, 0))
+        # F**_L: double-star momenta (3 mul); per component F*_L = F_L + S_L (U*-U)
+        # and F** = F* + S*_L (U** - U*) (4 add 2 mul), 7 components
+        sel = tot((0, 3, 0, 0), times((4, 2, 0, 0), 7))
+        rs = tot(head, times(star, 2), alf, sel)
+    face = tot(plm, common, rs)
+    faces = times(face, dim)
+    # one edge: four reconstructions toward the edge (6 add 4 mul each, the same
+    # pattern as PLM), then the upwind average: two brackets (4 add 6 mul 1 div
+    # each) and their difference (1 add)
+    edge = tot(times((6, 4, 0, 0), 4), times((4, 6, 1, 0), 2), (1, 0, 0, 0))
+    emf = times(edge, 3 if dim == 3 else 1)
+    if dim == 3:
+        # five cell fields: three differences, three divisions, two sums;
+        # three face fields: two differences, two divisions, one difference
+        upd = tot(times((5, 0, 3, 0), 5), times((3, 0, 2, 0), 3))
+    else:
+        # six cell fields (with B_z): two differences, two divisions, one sum;
+        # b_x and b_y: one difference, one division each
+        upd = tot(times((3, 0, 2, 0), 6), times((1, 0, 1, 0), 2))
+    return {"prims": prims, "faces": faces, "emf": emf, "update": upd}
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("solver", ["hll", "hlld"])
+def test_count_ops_matches_hand_count(dim, solver):
+    """The oracle's operation counter (which states the algorithmic flops per
+    cell behind the ALU roofline) against a hand count of one PLM face, one
+    HLL or HLLD solve, one upwind edge and one update, on a uniform state at
+    rest where every cell takes the same branches."""
+    s, U = W.uniform(dim=dim, n=4, v=(0.0, 0.0, 0.0), B=(0.9, -0.6, 0.7), p=0.3, rho=1.2)
+    s = dict(s, riemann=solver)
+    cells = U[0].size
+    got = O.count_ops(O.cfg_from(s), U)
+    want = _hand_count_uniform(dim, solver)
+    kinds = ("add", "mul", "div", "sqrt")
+    for ph, w in want.items():
+        assert tuple(got[ph][k] for k in kinds) == tuple(cells * x for x in w), (ph, got[ph], w)
