@@ -105,6 +105,25 @@ mhd_status mhd_dt(mhd_ctx* ctx, const double* U, void* ws, size_t ws_bytes, doub
 mhd_status mhd_dt_device(mhd_ctx* ctx, const double* U, void* ws, size_t ws_bytes, double* dt_dev,
                          void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the time step of
+ * mhd_dt_device (the same value, bit for bit) without a workspace. Its
+ * scratch, the per-block partials of the reduction (at most 2048 doubles)
+ * and the unphysical flag, is a file-scope device array of 16.6 KB that each
+ * GPU the library runs on holds until the process ends; the library finds
+ * its address on the first call made with a device current. The reduction
+ * strides over the grid, so every grid mhd_init accepts fits. The caller
+ * passes U and the device double *dt_dev; *flag_dev (a device int32, NULL
+ * to skip) receives 1 if a cell of U had rho <= 0, p <= 0 or a non-finite
+ * value in this call, else 0 (unlike the workspace flag, it is not sticky).
+ * No allocation, no host synchronisation; the current device must be the one
+ * that holds U and the stream. Calls that overlap on one GPU share the array
+ * and race: serialise them (one stream, or events). MHD_ERR_INVALID for a
+ * null ctx, U or dt_dev; MHD_ERR_DEVICE if the array's address cannot be
+ * found or a launch fails. */
+mhd_status mhd_dt_device_noalloc(mhd_ctx* ctx, const double* U, double* dt_dev,
+                                 int32_t* flag_dev, void* stream);
+
 /* One step of size dt, in place. SSP-RK2:
  *   U1 = U + dt L(U);  U <- (U + (U1 + dt L(U1))) / 2;
  * SSP-RK3 (Sec. 2.2 Eq. (RK3), read as the Shu-Osher scheme):

@@ -298,6 +298,27 @@ mhd_status mhd_dt_device(mhd_ctx* ctx, const double* U, void* ws, size_t ws_byte
   return cfl_to(ctx, U, ws, dt_dev, static_cast<hipStream_t>(stream));
 }
 
+mhd_status mhd_dt_device_noalloc(mhd_ctx* ctx, const double* U, double* dt_dev,
+                                 int32_t* flag_dev, void* stream) {
+  if (!ctx) return MHD_ERR_INVALID;
+  if (!U || !dt_dev) return MHD_ERR_INVALID;
+  mhd::CflArgs a{};
+  a.dim = ctx->cfg.dim;
+  a.g = ctx->g;
+  a.U = U;
+  // the reduction strides over the grid, so every valid grid fits in the
+  // array's partials; small grids take fewer blocks
+  const int64_t need = (ctx->g.n + 255) / 256;
+  a.nblocks = (int)std::min<int64_t>(need, mhd::kNoAllocPartials);
+  a.cfl = ctx->cfg.cfl;
+  a.dt_out = dt_dev;
+  a.stream = static_cast<hipStream_t>(stream);
+  a.timer = ctx->timer;
+  hipError_t e = mhd::launch_cfl_noalloc(a, flag_dev);
+  if (e != hipSuccess) return device_fail(ctx, e, "cfl (no workspace)");
+  return MHD_OK;
+}
+
 mhd_status mhd_dt(mhd_ctx* ctx, const double* U, void* ws, size_t ws_bytes, double* dt_out,
                   void* stream) {
   if (!ctx) return MHD_ERR_INVALID;

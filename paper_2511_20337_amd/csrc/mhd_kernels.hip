@@ -15,6 +15,8 @@
 //
 // Layout: state and workspace arrays are field-major SoA, x fastest, so a
 // wavefront of 64 consecutive cells reads 512 contiguous bytes per field.
+#include <mutex>
+
 #include "mhd_device.hpp"
 #include "mhd_grid.hpp"
 #include "mhd_kernels.hpp"
@@ -1052,6 +1054,72 @@ size_t stage_cfl_blocks(const Geom& g, int limiter) {
 
 hipError_t launch_stage(const StageArgs& a) {
   return (a.dim == 3) ? stage_lim<3>(a) : stage_lim<2>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free CFL time step (mhd_dt_device_noalloc). Its per-block
+// partials and the unphysical flag live in this file-scope device array
+// instead of the caller's workspace: kNoAllocPartials doubles, then the flag
+// (an int) in the next double. Every device holds its own copy at its own
+// address, found with hipGetSymbolAddress on the first call made with that
+// device current; host code uses only that address, never the array's name.
+// Calls that overlap on one device share the array and race.
+static __device__ __align__(256) double scratch[kNoAllocPartials + 32];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+hipError_t scratch_here(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+// The flag must start each call at zero: a kernel clears it (no memset, so
+// that a captured graph replays the clear correctly).
+__global__ void k_flag_clear(int* __restrict__ flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+
+__global__ void k_flag_copy(const int* __restrict__ flag, int32_t* __restrict__ out) {
+  if (threadIdx.x == 0) *out = *flag;
+}
+
+}  // namespace
+
+hipError_t launch_cfl_noalloc(const CflArgs& a, int32_t* flag_out) {
+  if (a.nblocks < 1 || a.nblocks > kNoAllocPartials) return hipErrorInvalidValue;
+  double* base = nullptr;
+  hipError_t e = scratch_here(&base);
+  if (e != hipSuccess) return e;
+  int* flag = reinterpret_cast<int*>(base + kNoAllocPartials);
+  hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, a.stream, flag);
+  if (a.dim == 3)
+    MHD_TIMED(a, K_CFL,
+              hipLaunchKernelGGL((k_cfl<3>), dim3(a.nblocks), dim3(kBlock), 0, a.stream, a.U, a.g,
+                                 base, flag));
+  else
+    MHD_TIMED(a, K_CFL,
+              hipLaunchKernelGGL((k_cfl<2>), dim3(a.nblocks), dim3(kBlock), 0, a.stream, a.U, a.g,
+                                 base, flag));
+  MHD_TIMED(a, K_CFL_FINAL,
+            hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, base, a.nblocks,
+                               a.cfl, a.dt_out));
+  if (flag_out) hipLaunchKernelGGL(k_flag_copy, dim3(1), dim3(64), 0, a.stream, flag, flag_out);
+  return hipGetLastError();
 }
 
 hipError_t launch_cfl(const CflArgs& a) {

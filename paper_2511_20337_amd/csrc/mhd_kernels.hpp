@@ -68,5 +68,12 @@ hipError_t launch_stage(const StageArgs& a);
 // number of CFL partials the 3D face kernel writes (one per workgroup)
 size_t stage_cfl_blocks(const Geom& g, int limiter);
 hipError_t launch_cfl(const CflArgs& a);
+// Partials of the allocation-free CFL time step (a file-scope device array of
+// that many doubles plus the flag; nblocks must not exceed it).
+constexpr int kNoAllocPartials = 2048;
+// The CFL time step with the partials and the flag in that array (a.partial
+// and a.flag are ignored); flag_out (device int32, nullable) receives 1 if
+// any cell was unphysical in this call, else 0.
+hipError_t launch_cfl_noalloc(const CflArgs& a, int32_t* flag_out);
 
 }  // namespace mhd

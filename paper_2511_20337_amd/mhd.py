@@ -30,7 +30,8 @@ INTEGRATORS = {"rk2": 0, "rk3": 1}
 
 # Every symbol include/mhd.h declares.
 SYMBOLS = ("mhd_init", "mhd_destroy", "mhd_workspace_bytes", "mhd_dt", "mhd_dt_device",
-           "mhd_step", "mhd_step_device_dt", "mhd_step_cfl", "mhd_rhs", "mhd_adjoint_step",
+           "mhd_dt_device_noalloc", "mhd_step", "mhd_step_device_dt", "mhd_step_cfl", "mhd_rhs",
+           "mhd_adjoint_step",
            "mhd_adjoint_step_device", "mhd_check",
            "mhd_timing", "mhd_timing_read", "mhd_strerror", "mhd_last_error")
 
@@ -76,6 +77,7 @@ def lib():
             "mhd_workspace_bytes": ([vp, ctypes.c_int32], sz),
             "mhd_dt": ([vp, vp, vp, sz, dp, vp], st),
             "mhd_dt_device": ([vp, vp, vp, sz, vp, vp], st),
+            "mhd_dt_device_noalloc": ([vp, vp, vp, vp, vp], st),
             "mhd_step": ([vp, vp, ctypes.c_double, vp, sz, vp], st),
             "mhd_step_device_dt": ([vp, vp, vp, vp, sz, vp], st),
             "mhd_step_cfl": ([vp, vp, vp, vp, sz, vp], st),
@@ -157,6 +159,14 @@ def mhd_dt_device(ctx, U, ws, dt_dev) -> None:
     rc = lib().mhd_dt_device(ctx, U.data_ptr(), ws.data_ptr(), ws.numel(), dt_dev.data_ptr(),
                              _stream(U.device))
     _raise(ctx, rc, "mhd_dt_device")
+
+
+def mhd_dt_device_noalloc(ctx, U, dt_dev, flag_dev=None) -> None:
+    """dt_dev: float64 device tensor; flag_dev: int32 device tensor or None."""
+    rc = lib().mhd_dt_device_noalloc(ctx, U.data_ptr(), dt_dev.data_ptr(),
+                                     None if flag_dev is None else flag_dev.data_ptr(),
+                                     _stream(U.device))
+    _raise(ctx, rc, "mhd_dt_device_noalloc")
 
 
 def mhd_step(ctx, U, dt: float, ws) -> None:
