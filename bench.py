@@ -40,30 +40,49 @@ def log(*a):
     print("[%6.1f s]" % (time.perf_counter() - _T0), *a, file=sys.stderr, flush=True)
 
 
-# Algorithmic work of one launch of each forward kernel, per cell (3D):
-#  bytes: what the kernel must read and write once (halo re-reads excluded);
-#  flops: FP64 operations of the method's definition (add/sub, mul, div, sqrt
-#         each one), counted by oracle/count_flops.py on this workload.
-KERNEL_BYTES = {"faces": 8 * (8 + 27),          # read U, write 3 x 9 face values
-                "emf": 8 * (12 + 3 + 3),        # read alpha+-, 2 velocities per face, b; write E
-                "update": 8 * (15 + 3 + 8 + 8 + 8),  # fluxes, E, U, U0 (stage 2), write
-                "cfl": 8 * 8}
-KERNEL_FLOPS = {"faces": 1336.5, "emf": 277.7, "update": 55.0}
-KERNEL_BOUND = {"faces": "alu", "emf": "hbm", "update": "hbm", "cfl": "hbm"}
-# HBM bytes per cell of one launch measured with rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (scaled by the copy-kernel calibration, 2.0 and 1.0), for the
-# kernels as they stand; see profiles/.
-KERNEL_TRAFFIC = {"faces": 202.4 + 216.0}
-# Mixed mode: the face kernel reads the FP64 state and writes its 27 records in
-# FP32; it is bound by HBM (see profiles/), so its roofline entry is in bytes.
-KERNEL_BYTES_MIXED = {"faces": 8 * 8 + 4 * 27}
-KERNEL_TRAFFIC_MIXED = {"faces": 203.0 + 108.0}
+# Roofline of the dominant kernel, the face kernel (reconstruction + Riemann
+# solve of every lower face, with primitive recovery), per cell:
+#  flops: operations of the method's definition in those phases (add/sub, mul,
+#         div, sqrt one each), counted by oracle/count_flops.py on the initial
+#         state of this workload at 256^3 (3D turbulence, van Leer, HLLD);
+#  bytes: the state it must read once, 64 B; the face records it writes are an
+#         artefact of splitting the stage into kernels, not algorithmic traffic.
+# The kernel's roof is the slower of the two: flops at the vector peak of the
+# arithmetic's precision (FP64 78.6 TFLOP/s; FP32 157.3 in the mixed mode) or
+# bytes at 8 TB/s; frac = that time / the measured time per launch.
+FACE_FLOPS = 1343.8
+FACE_BYTES = 64
+FP32_PEAK = 157.3e12
+# HBM bytes per cell of one face-kernel launch, rocprofv3 FETCH_SIZE x 2.0 and
+# WRITE_SIZE x 1.0 (the copy-kernel calibration), for the kernel as it stands.
+FACE_TRAFFIC = {"fp64": 202.4 + 216.0, "mixed": 203.0 + 108.0}
 # WENO-Z face kernel on the 3D Orszag-Tang problem (FP64, HLLD): algorithmic
-# flops per cell of the oracle's face phase on that workload at 64^3 (count_flops.py;
+# flops per cell of the oracle's face phase on that workload at 256^3 (count_flops.py;
 # its textbook WENO-Z with seven divisions per value, each one flop), and the
 # HBM bytes per cell counted at 352^3 (reads past L2 x2.0, writes x1.0).
-WENO_FACE_FLOPS = 4039.2
+WENO_FACE_FLOPS = 4039.4
 WENO_FACE_TRAFFIC = 380.6 + 216.0
+
+
+def face_roofline(kt, ncell, precision="fp64"):
+    """Roofline entry of the face kernel from its HIP-event times."""
+    tot_ms, launches = kt["faces"]
+    avg_s = tot_ms / launches / 1e3
+    fpeak = FP64_PEAK if precision == "fp64" else FP32_PEAK
+    t_alu = FACE_FLOPS * ncell / fpeak
+    t_hbm = FACE_BYTES * ncell / HBM_PEAK
+    traffic = FACE_TRAFFIC[precision] * ncell
+    out = {"kernel": "faces", "avg_launch_ms": avg_s * 1e3, "flops_per_cell": FACE_FLOPS,
+           "bytes_per_cell": FACE_BYTES, "traffic": traffic, "traffic_unit": "bytes per launch",
+           "hbm_counted_GBps": traffic / avg_s / 1e9,
+           "alu_frac": t_alu / avg_s, "hbm_frac": t_hbm / avg_s}
+    if t_alu >= t_hbm:
+        out.update({"bound": "alu", "achieved": FACE_FLOPS * ncell / avg_s / 1e12,
+                    "peak": fpeak / 1e12, "unit": "TFLOP/s", "frac": t_alu / avg_s})
+    else:
+        out.update({"bound": "hbm", "achieved": FACE_BYTES * ncell / avg_s / 1e9,
+                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": t_hbm / avg_s})
+    return out
 
 
 def time_gpu(setup, U0, steps, warmup, timing=True):
@@ -201,9 +220,9 @@ def only_part(part, n, steps, warmup):
                "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]}}
     elif part == "ot3d_wenoz":
         so, Uo = W.orszag_tang_3d(n, limiter="wenoz")
-        el, kt, _, phys = time_gpu(dict(so, integrator="rk3"), Uo, steps, warmup)
+        el, kt, _, phys = time_gpu(dict(so, integrator="rk3", emf="uct_hlld"), Uo, steps, warmup)
         out = {"part": part, "value": n ** 3 * steps / el / 1e6, "unit": "Mcell-updates/s",
-               "workload": "orszag_tang_3d_%d wenoz ssp_rk3 hlld" % n, "physical": phys,
+               "workload": "orszag_tang_3d_%d wenoz ssp_rk3 hlld uct_hlld" % n, "physical": phys,
                "ms_per_step": el / steps * 1e3,
                "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]},
                "roofline": weno_roofline(kt, n ** 3)}
@@ -259,26 +278,7 @@ def main(argv=None):
     value = ncell * args.steps / elapsed / 1e6
     ms_per_step = elapsed / args.steps * 1e3
 
-    # dominant kernel by total event time
-    dom = max(kt.items(), key=lambda kv: kv[1][0])
-    name, (tot_ms, launches) = dom
-    avg_s = tot_ms / launches / 1e3
-    bound = KERNEL_BOUND.get(name, "hbm")
-    bpc = KERNEL_BYTES.get(name, 0)
-    traffic = KERNEL_TRAFFIC.get(name)
-    if bound == "alu":
-        achieved = KERNEL_FLOPS[name] * ncell / avg_s
-        roofline = {"kernel": name, "bound": "alu", "achieved": achieved / 1e12,
-                    "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK}
-    else:
-        achieved = bpc * ncell / avg_s
-        roofline = {"kernel": name, "bound": "hbm", "achieved": achieved / 1e9,
-                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK}
-    roofline.update({"traffic": traffic * ncell if traffic else None,
-                     "traffic_unit": "bytes per launch", "avg_launch_ms": avg_s * 1e3,
-                     "flops_per_cell": KERNEL_FLOPS.get(name), "bytes_per_cell": bpc,
-                     "hbm_algorithmic_GBps": bpc * ncell / avg_s / 1e9,
-                     "hbm_counted_GBps": traffic * ncell / avg_s / 1e9 if traffic else None})
+    roofline = face_roofline(kt, ncell)
     kernels = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "share": v[0] / sum(x[0] for x in kt.values())}
                for k, v in kt.items() if v[1]}
 
@@ -310,20 +310,9 @@ def main(argv=None):
         el_m, kt_m, _, phys_m = time_gpu(sm, Um, args.steps, args.warmup)
         del Um
         vm = ncell * args.steps / el_m / 1e6
-        tot_m, nl_m = kt_m["faces"]
-        avg_m = tot_m / nl_m / 1e3
-        ach_m = KERNEL_BYTES_MIXED["faces"] * ncell / avg_m
-        tr_m = KERNEL_TRAFFIC_MIXED["faces"]
         out["mixed"] = {"value": vm, "unit": "Mcell-updates/s", "ms_per_step": el_m / args.steps * 1e3,
                         "hbm_roofline_frac_step": vm * 1e6 * STEP_BYTES / HBM_PEAK,
-                        "roofline": {"kernel": "faces", "bound": "hbm", "achieved": ach_m / 1e9,
-                                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                                     "frac": ach_m / HBM_PEAK,
-                                     "traffic": tr_m * ncell if tr_m else None,
-                                     "traffic_unit": "bytes per launch",
-                                     "avg_launch_ms": avg_m * 1e3,
-                                     "bytes_per_cell": KERNEL_BYTES_MIXED["faces"],
-                                     "hbm_counted_GBps": tr_m * ncell / avg_m / 1e9 if tr_m else None},
+                        "roofline": face_roofline(kt_m, ncell, "mixed"),
                         "physical": phys_m,
                         "config": {"workload": "turbulence_3d_lowbeta_%d" % args.n, "mach": 3,
                                    "beta": 0.01, "precision": "mixed"},
@@ -355,7 +344,7 @@ def main(argv=None):
             "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_o.items() if v[1]},
             "paper_context": {"value": 37.8, "unit": "Mcell-updates/s per GPU",
                               "hardware": "NVIDIA H100 (4 per node)",
-                              "scheme": "WENO-Z + RK3 + HLLD + CT, FP64",
+                              "scheme": "WENO-Z + RK3 + HLLD + CT (UCT-HLLD), FP64",
                               "note": "context only: another scheme on other hardware"}}
         log("the same with SSP-RK3, the paper's integrator")
         so3, Uo3 = W.orszag_tang_3d(352)
@@ -366,9 +355,9 @@ def main(argv=None):
             "value": 352 ** 3 * steps_o / el_o3 / 1e6, "unit": "Mcell-updates/s",
             "ms_per_step": el_o3 / steps_o * 1e3, "physical": phys_o3,
             "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_o3.items() if v[1]}}
-        log("the same with the paper's scheme: WENO-Z + SSP-RK3 + HLLD + CT")
+        log("the same with the paper's scheme: WENO-Z + SSP-RK3 + HLLD + CT (UCT-HLLD)")
         sow, Uow = W.orszag_tang_3d(352, limiter="wenoz")
-        sow = dict(sow, integrator="rk3")
+        sow = dict(sow, integrator="rk3", emf="uct_hlld")
         el_ow, kt_ow, _, phys_ow = time_gpu(sow, Uow, steps_o, 1)
         del Uow
         out["orszag_tang_3d"]["wenoz_rk3"] = {

@@ -67,6 +67,29 @@ typedef enum { MHD_PREC_FP64 = 0, MHD_PREC_MIXED = 1 } mhd_precision;
 /* Time integrator: the two-stage SSP Runge-Kutta scheme, or the three-stage
  * one of Sec. 2.2 Eq. (RK3) (Shu & Osher). */
 typedef enum { MHD_SSP_RK2 = 0, MHD_SSP_RK3 = 1 } mhd_integrator;
+/* Edge EMF of constrained transport (Sec. 2.2, CT; the runs of Secs. 4.1-4.2
+ * use the UCT-HLLD average, whose formulas the paper does not print):
+ * MHD_EMF_UCT_HLL, an upwind average whose weights are the HLL wave-speed
+ * bounds of the faces touching the edge (maximised over the two faces);
+ * MHD_EMF_UCT_HLLD, an upwind average whose weights and diffusion
+ * coefficients are those of the face's Riemann flux of the transverse field
+ * (averaged over the two faces), so that with HLLD fluxes and plane-parallel
+ * data the EMF is minus the HLLD flux of the transverse field. The adjoint
+ * supports MHD_EMF_UCT_HLL only. */
+typedef enum { MHD_EMF_UCT_HLL = 0, MHD_EMF_UCT_HLLD = 1 } mhd_emf;
+/* Control of div B (Sec. 2.1 lists divergence cleaning beside CT; the
+ * strong-scaling runs of Secs. 4.1-4.2 use it): MHD_DIVB_CT, the staggered
+ * field with constrained transport; MHD_DIVB_GLM, the mixed GLM cleaning of
+ * Dedner et al. (2002) on a cell-centred field with a ninth field psi:
+ *   dB/dt + div(vB - Bv) + grad psi = 0,  dpsi/dt + c_h^2 div B = damping,
+ * with the (B_n, psi) face problem solved exactly, c_h = C Delta_min / dt (the
+ * largest speed the step's dt allows) and psi multiplied by
+ * exp(-alpha c_h dt / Delta_min), alpha = 0.1, after each step. With GLM the
+ * state holds NINE fields, 9*nz*ny*nx doubles in the order rho, m_x, m_y,
+ * m_z, E, B_x, B_y, B_z, psi, all cell-centred; emf must be MHD_EMF_UCT_HLL
+ * (it is not used). mhd_rhs, the adjoint and mhd_dt_device_noalloc return
+ * MHD_ERR_UNSUPPORTED with GLM. */
+typedef enum { MHD_DIVB_CT = 0, MHD_DIVB_GLM = 1 } mhd_divb;
 
 typedef struct {
   int32_t dim;                  /* 2 or 3 */
@@ -78,6 +101,8 @@ typedef struct {
   int32_t riemann;              /* mhd_riemann */
   int32_t precision;            /* mhd_precision */
   int32_t integrator;           /* mhd_integrator (0, the former reserved field, is SSP-RK2) */
+  int32_t emf;                  /* mhd_emf (0: MHD_EMF_UCT_HLL) */
+  int32_t divb;                 /* mhd_divb (0: MHD_DIVB_CT) */
 } mhd_config;
 
 typedef struct mhd_ctx mhd_ctx;
@@ -157,8 +182,8 @@ mhd_status mhd_rhs(mhd_ctx* ctx, const double* U, double* L, void* ws, size_t ws
  * non-NULL, the host double *dtbar = (dPhi/d dt)^T Ubar_np1 (this one
  * synchronises). Not part of the paper: the derivative of every
  * non-smooth point (limiter at extrema, min/max, Riemann region switches) is
- * that of the branch the forward step takes. FP64 and PLM, with either
- * integrator (MHD_ERR_UNSUPPORTED otherwise). Ubar_n must not
+ * that of the branch the forward step takes. FP64, PLM and MHD_EMF_UCT_HLL,
+ * with either integrator (MHD_ERR_UNSUPPORTED otherwise). Ubar_n must not
  * alias Ubar_np1 or U_n. Needs mhd_workspace_bytes(ctx, 1). */
 mhd_status mhd_adjoint_step(mhd_ctx* ctx, const double* U_n, double dt, const double* Ubar_np1,
                             double* Ubar_n, double* dtbar, void* ws, size_t ws_bytes,

@@ -28,6 +28,7 @@ LIMITERS = {"minmod": 0, "vanleer": 1, "wenoz": 2}
 SOLVERS = {"hlld": 0, "hll": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 INTEGRATORS = {"rk2": 0, "rk3": 1}
+EMFS = {"uct_hll": 0, "uct_hlld": 1}
 
 
 class OCfg(ctypes.Structure):
@@ -41,6 +42,7 @@ class OCfg(ctypes.Structure):
         ("limiter", ctypes.c_int32), ("riemann", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("nthreads", ctypes.c_int32),
         ("integrator", ctypes.c_int32),
+        ("emf", ctypes.c_int32),
     ]
 
 
@@ -74,6 +76,13 @@ def _load():
             ("oracle_run_dts", [cp, dp, ctypes.c_int, dp], ctypes.c_int),
             ("oracle_step_jvp", [cp, dp, dp, ctypes.c_double, ctypes.c_double], ctypes.c_int),
             ("oracle_divb", [cp, dp, dp], ctypes.c_int),
+            ("oracle_glm_dt", [cp, dp, dp], ctypes.c_int),
+            ("oracle_glm_run", [cp, dp, ctypes.c_int, dp], ctypes.c_int),
+            ("oracle_glm_run_dts", [cp, dp, ctypes.c_int, dp], ctypes.c_int),
+            ("oracle_glm_rhs", [cp, dp, dp, ctypes.c_double], ctypes.c_int),
+            ("oracle_glm_face", [ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, dp], ctypes.c_int),
             ("oracle_prim", [cp, dp, dp], ctypes.c_int),
             ("oracle_riemann", [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
                                 ctypes.c_double, dp], ctypes.c_int),
@@ -121,7 +130,7 @@ def cfg_from(setup: dict, nthreads: int = 0, **over) -> OCfg:
                 float(s["gamma"]), float(s["cfl"]),
                 LIMITERS[s["limiter"]], SOLVERS[s["riemann"]],
                 PRECISIONS[s.get("precision", "fp64")], int(nthreads),
-                INTEGRATORS[s.get("integrator", "rk2")])
+                INTEGRATORS[s.get("integrator", "rk2")], EMFS[s.get("emf", "uct_hll")])
 
 
 def _shape(c: OCfg):
@@ -204,11 +213,12 @@ def prim(c: OCfg, U, allow_unphysical=False) -> np.ndarray:
 
 def riemann(wl, wr, bn, gamma=5.0 / 3.0, solver="hlld", precision="fp64") -> np.ndarray:
     """Single face problem. w = (rho, u, v, w, B_t1, B_t2, p).
-    Returns 11 values: flux of (rho, m_n, m_t1, m_t2, B_t1, B_t2, E),
-    alpha+, alpha-, vt1, vt2."""
+    Returns 16 values: flux of (rho, m_n, m_t1, m_t2, B_t1, B_t2, E),
+    alpha+, alpha-, the HLL-weighted vt1, vt2, then the UCT-HLLD coefficients
+    om, d^L, d^R and the om-weighted vt1, vt2."""
     wl = np.ascontiguousarray(wl, dtype=np.float64)
     wr = np.ascontiguousarray(wr, dtype=np.float64)
-    out = np.zeros(11)
+    out = np.zeros(16)
     _check(_load().oracle_riemann(SOLVERS[solver], PRECISIONS[precision], float(gamma),
                                   _ptr(wl), _ptr(wr), float(bn), _ptr(out)))
     return out
@@ -252,3 +262,64 @@ def count_ops(c: OCfg, U) -> dict:
     names = ("prims", "faces", "emf", "update")
     kinds = ("add", "mul", "div", "sqrt")
     return {names[p]: {kinds[k]: int(out[4 * p + k]) for k in range(4)} for p in range(4)}
+
+
+# ------------------------------------------------------- GLM cleaning ----
+GLM_ALPHA = 0.1  # damping of psi per step: exp(-GLM_ALPHA * c_h dt / min spacing)
+
+
+def _glm_state(c: OCfg, U) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    assert U.shape == (9, c.nz, c.ny, c.nx), U.shape
+    return U
+
+
+def glm_dt(c: OCfg, U) -> float:
+    out = ctypes.c_double(0.0)
+    _check(_load().oracle_glm_dt(ctypes.byref(c), _ptr(_glm_state(c, U)), ctypes.byref(out)))
+    return out.value
+
+
+def glm_run(c: OCfg, U, nsteps: int):
+    """nsteps GLM steps (CFL dt each); returns (state, dts)."""
+    U = _glm_state(c, U).copy()
+    dts = np.zeros(max(nsteps, 1))
+    _check(_load().oracle_glm_run(ctypes.byref(c), _ptr(U), int(nsteps), _ptr(dts)))
+    return U, dts[:nsteps]
+
+
+def glm_run_dts(c: OCfg, U, dts) -> np.ndarray:
+    U = _glm_state(c, U).copy()
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    _check(_load().oracle_glm_run_dts(ctypes.byref(c), _ptr(U), len(d), _ptr(d)))
+    return U
+
+
+def glm_rhs(c: OCfg, U, ch: float) -> np.ndarray:
+    U = _glm_state(c, U)
+    L = np.zeros_like(U)
+    _check(_load().oracle_glm_rhs(ctypes.byref(c), _ptr(U), _ptr(L), float(ch)))
+    return L
+
+
+def glm_face(wl, wr, bnl, bnr, psil, psir, ch, gamma=5.0 / 3.0, solver="hlld") -> np.ndarray:
+    """One GLM face: fluxes of (rho, m_n, m_t1, m_t2, B_t1, B_t2, E, B_n, psi)."""
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    out = np.zeros(9)
+    _check(_load().oracle_glm_face(SOLVERS[solver], float(gamma), _ptr(wl), _ptr(wr), float(bnl),
+                                   float(bnr), float(psil), float(psir), float(ch), _ptr(out)))
+    return out
+
+
+def divb_centred(c: OCfg, U) -> np.ndarray:
+    """Central-difference div B of a GLM state (cell-centred B), test-side."""
+    U = _glm_state(c, U)
+    dx = (c.xmax - c.xmin) / c.nx
+    dy = (c.ymax - c.ymin) / c.ny
+    dz = (c.zmax - c.zmin) / c.nz
+    d = (np.roll(U[5], -1, 2) - np.roll(U[5], 1, 2)) / (2 * dx) + \
+        (np.roll(U[6], -1, 1) - np.roll(U[6], 1, 1)) / (2 * dy)
+    if c.dim == 3:
+        d = d + (np.roll(U[7], -1, 0) - np.roll(U[7], 1, 0)) / (2 * dz)
+    return d

@@ -148,6 +148,7 @@ struct OCfg {
   int32_t precision;        // 0 FP64, 1 mixed (FP32 reconstruction/Riemann/EMF)
   int32_t nthreads;         // OpenMP threads (<= 0: library default)
   int32_t integrator;       // 0 SSP-RK2, 1 SSP-RK3
+  int32_t emf;              // 0 UCT-HLL, 1 UCT-HLLD
 };
 
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4, BX = 5, BY = 6, BZ = 7, NF = 8 };
@@ -246,6 +247,11 @@ template <class R> R wenoz_upper(R v0, R v1, R v2, R v3, R v4) {
 template <class R> struct RSOut {
   R F[7];
   R ap, am, vt1, vt2;
+  // UCT-HLLD coefficients (filled on request): the flux weight of the left
+  // state (that of the right one is 1 - om), the diffusion coefficients of
+  // the left and right transverse field, and the face velocities weighted by
+  // (om, 1 - om)
+  R om, dl, dr, wt1, wt2;
 };
 
 // Conserved vector, physical flux (Eq. mhd, projected on the normal) and total
@@ -282,8 +288,30 @@ template <class R> R fast_speed(R g, R rho, R p, R bn, R bt1, R bt2) {
 template <class R> struct DegTol { static constexpr double value = 1e-12; };
 template <> struct DegTol<float> { static constexpr double value = 1e-12 * 536870912.0; };
 
+// [reading] UCT-HLLD (the CT average the paper names for its runs; its
+// formulas are not in the paper). At the wave structure of a face (wave
+// speeds, contact speed, star densities and the per-side factors that map
+// B_t and v_t into the star states), the HLLD flux of each transverse field
+// component is linear in (B_t^L, B_t^R, v_t^L, v_t^R):
+//   F[B_t] = chiL B_t^L + chiR B_t^R - B_n (om v_t^L + (1 - om) v_t^R).
+// The upwind EMF takes om and 1 - om as the weights of the left and right
+// advective terms v_n B_t, d^L = chiL - om u_L and d^R = (1 - om) u_R - chiR
+// as the diffusion coefficients, and om v_t^L + (1 - om) v_t^R as the face
+// velocity, so that plane-parallel data give E = -F_HLLD[B_t] exactly. For the
+// HLL flux the same construction gives om = alpha+/(alpha+ + alpha-),
+// d^L = d^R = alpha+ alpha-/(alpha+ + alpha-).
 template <class R>
-void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
+void uct_hll_coeffs(const R wl[7], const R wr[7], RSOut<R>& o) {
+  o.om = o.ap / (o.ap + o.am);
+  o.dl = o.ap * o.am / (o.ap + o.am);
+  o.dr = o.dl;
+  o.wt1 = o.om * wl[2] + (R(1) - o.om) * wr[2];
+  o.wt2 = o.om * wl[3] + (R(1) - o.om) * wr[3];
+}
+
+template <class R>
+void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o,
+             bool uct_hlld = false) {
   R UL[7], FL[7], UR[7], FR[7], ptl, ptr;
   state_of(g, wl, bn, UL, FL, ptl);
   state_of(g, wr, bn, UR, FR, ptr);
@@ -301,6 +329,7 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
   o.vt2 = (o.ap * wl[3] + o.am * wr[3]) / (o.ap + o.am);
 
   if (solver == 1) {  // HLL: single intermediate state
+    if (uct_hlld) uct_hll_coeffs(wl, wr, o);
     if (SL >= R(0)) { for (int q = 0; q < 7; ++q) o.F[q] = FL[q]; return; }
     if (SR <= R(0)) { for (int q = 0; q < 7; ++q) o.F[q] = FR[q]; return; }
     for (int q = 0; q < 7; ++q)
@@ -309,8 +338,16 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
   }
 
   // HLLD (Miyoshi & Kusano 2005): four intermediate states.
-  if (SL > R(0)) { for (int q = 0; q < 7; ++q) o.F[q] = FL[q]; return; }
-  if (SR < R(0)) { for (int q = 0; q < 7; ++q) o.F[q] = FR[q]; return; }
+  if (SL > R(0)) {
+    for (int q = 0; q < 7; ++q) o.F[q] = FL[q];
+    if (uct_hlld) { o.om = R(1); o.dl = R(0); o.dr = R(0); o.wt1 = wl[2]; o.wt2 = wl[3]; }
+    return;
+  }
+  if (SR < R(0)) {
+    for (int q = 0; q < 7; ++q) o.F[q] = FR[q];
+    if (uct_hlld) { o.om = R(0); o.dl = R(0); o.dr = R(0); o.wt1 = wr[2]; o.wt2 = wr[3]; }
+    return;
+  }
 
   // contact speed and total pressure of the star region
   const R sdl = SL - ul, sdr = SR - ur;
@@ -322,6 +359,7 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
   // single-star states on each side
   R Us[2][7];
   R rhos[2], vs[2], ws[2], b1s[2], b2s[2];
+  R zeta[2], eta[2];  // B*_t = zeta B_t, v*_t = v_t - eta B_t (per side)
   const R* wlr[2] = {wl, wr};
   const R* Ulr[2] = {UL, UR};
   const R Slr[2] = {SL, SR};
@@ -339,6 +377,8 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
     // units, scaled to the working precision (x 2^29 in FP32)
     if (Abs(D) <= R(DegTol<R>::value) * (Abs(big) + bn * bn)) {
       vs[s] = w[2]; ws[s] = w[3]; b1s[s] = w[4]; b2s[s] = w[5];
+      zeta[s] = R(1);
+      eta[s] = R(0);
     } else {
       const R fv = bn * (SM - w[1]) / D;
       vs[s] = w[2] - w[4] * fv;
@@ -346,6 +386,8 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
       const R fb = (w[0] * su * su - bn * bn) / D;
       b1s[s] = w[4] * fb;
       b2s[s] = w[5] * fb;
+      zeta[s] = fb;
+      eta[s] = fv;
     }
     const R vb = w[1] * bn + w[2] * w[4] + w[3] * w[5];
     const R vbs = SM * bn + vs[s] * b1s[s] + ws[s] * b2s[s];
@@ -376,12 +418,38 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
   const R Essl = Us[0][6] - sgn * sql * ((vs[0] * b1s[0] + ws[0] * b2s[0]) - vbss);
   const R Essr = Us[1][6] + sgn * sqr * ((vs[1] * b1s[1] + ws[1] * b2s[1]) - vbss);
 
-  // region selection; ties go to the left (the flux is continuous there)
-  if (SLs >= R(0)) {                       // F*_L
+  // region: 3 F*_L, 4 F**_L, 5 F**_R, 6 F*_R; ties go to the left (the flux
+  // is continuous there)
+  const int region = (SLs >= R(0)) ? 3 : (SM >= R(0)) ? 4 : (SRs >= R(0)) ? 5 : 6;
+  if (uct_hlld) {
+    // the HLLD flux of one transverse field component at this wave
+    // structure, as a function of (B_t^L, B_t^R, v_t^L, v_t^R)
+    auto bt_flux = [&](R BL, R BR, R vL, R vR) {
+      const R FLt = ul * BL - vL * bn, FRt = ur * BR - vR * bn;
+      const R BsL = zeta[0] * BL, BsR = zeta[1] * BR;
+      const R vsL = vL - eta[0] * BL, vsR = vR - eta[1] * BR;
+      const R Bss = (sql * BsR + sqr * BsL + sgn * sql * sqr * (vsR - vsL)) * isum;
+      if (region == 3) return FLt + SL * (BsL - BL);
+      if (region == 4) return FLt + SL * (BsL - BL) + SLs * (Bss - BsL);
+      if (region == 5) return FRt + SR * (BsR - BR) + SRs * (Bss - BsR);
+      return FRt + SR * (BsR - BR);
+    };
+    const R chiL = bt_flux(R(1), R(0), R(0), R(0));
+    const R chiR = bt_flux(R(0), R(1), R(0), R(0));
+    // om from the coefficient of v_t^L, -B_n om; with B_n = 0 only the F* regions
+    // occur and the star side alone carries the flux
+    if (bn > R(0) || bn < R(0)) o.om = -bt_flux(R(0), R(0), R(1), R(0)) / bn;
+    else o.om = (region == 3) ? R(1) : R(0);
+    o.dl = chiL - o.om * ul;
+    o.dr = (R(1) - o.om) * ur - chiR;
+    o.wt1 = o.om * wl[2] + (R(1) - o.om) * wr[2];
+    o.wt2 = o.om * wl[3] + (R(1) - o.om) * wr[3];
+  }
+  if (region == 3) {                       // F*_L
     for (int q = 0; q < 7; ++q) o.F[q] = FL[q] + SL * (Us[0][q] - UL[q]);
     return;
   }
-  if (SM >= R(0)) {                        // F**_L
+  if (region == 4) {                       // F**_L
     const R Uss[7] = {rhos[0], rhos[0] * SM, rhos[0] * vss, rhos[0] * wss, b1ss, b2ss, Essl};
     for (int q = 0; q < 7; ++q) {
       const R Fs = FL[q] + SL * (Us[0][q] - UL[q]);
@@ -389,7 +457,7 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o) {
     }
     return;
   }
-  if (SRs >= R(0)) {                       // F**_R
+  if (region == 5) {                       // F**_R
     const R Uss[7] = {rhos[1], rhos[1] * SM, rhos[1] * vss, rhos[1] * wss, b1ss, b2ss, Essr};
     for (int q = 0; q < 7; ++q) {
       const R Fs = FR[q] + SR * (Us[1][q] - UR[q]);
@@ -412,6 +480,18 @@ template <class R>
 R uct_emf(R apa, R ama, R vW, R bW, R vE, R bE, R apb, R amb, R vS, R bS, R vN, R bN) {
   const R ta = (apa * vW * bW + ama * vE * bE - apa * ama * (bE - bW)) / (apa + ama);
   const R tb = (apb * vS * bS + amb * vN * bN - apb * amb * (bN - bS)) / (apb + amb);
+  return tb - ta;
+}
+
+// UCT-HLLD edge EMF [reading: the coefficients of the two faces touching the
+// edge are averaged]. a-bracket: weights (aa, 1 - aa) and diffusion
+// coefficients dla, dra from the a-faces, applied to v_a B_b on the two
+// b-faces reconstructed along a (W, E); b-bracket likewise.
+template <class R>
+R uct_hlld_emf(R aa, R dla, R dra, R vW, R bW, R vE, R bE, R ab, R dlb, R drb, R vS, R bS, R vN,
+               R bN) {
+  const R ta = aa * vW * bW + (R(1) - aa) * vE * bE - (dra * bE - dla * bW);
+  const R tb = ab * vS * bS + (R(1) - ab) * vN * bN - (drb * bN - dlb * bS);
   return tb - ta;
 }
 
@@ -463,13 +543,17 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
   // --- per direction: reconstruction + Riemann solve at every lower face ---
   // Face arrays: flux of the eight stored components in the global frame
   // (promoted to S), alpha+-, and the HLL-weighted velocity (global comps).
+  // With the UCT-HLLD average, Ap/Am hold its weight om and diffusion
+  // coefficient d^L, Dr its d^R, and Vt the om-weighted velocities.
+  const bool uh = cfg.emf == 1;
   std::vector<S> Fl[3];
-  std::vector<R> Ap[3], Am[3], Vt[3];
+  std::vector<R> Ap[3], Am[3], Vt[3], Dr[3];
   for (int d = 0; d < dim; ++d) {
     Fl[d].assign((size_t)NF * n, S(0));
     Ap[d].assign(n, R(0));
     Am[d].assign(n, R(0));
     Vt[d].assign((size_t)3 * n, R(0));
+    if (uh) Dr[d].assign(n, R(0));
     const int t1 = t1_of(d), t2 = t2_of(d);
     const int vn = VVX + d, vt1 = VVX + t1, vt2 = VVX + t2;
     const int bt1 = VBX + t1, bt2 = VBX + t2;
@@ -498,7 +582,7 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
           }
           const R bn = Cast<R>::of(F(BX + d)[c0]);  // staggered normal field
           RSOut<R> o;
-          riemann<R>(cfg.riemann, gR, wl, wr, bn, o);
+          riemann<R>(cfg.riemann, gR, wl, wr, bn, o, uh);
           S* fl = Fl[d].data();
           fl[(size_t)RHO * n + c0] = Cast<S>::of(o.F[0]);
           fl[(size_t)(MX + d) * n + c0] = Cast<S>::of(o.F[1]);
@@ -508,10 +592,18 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
           fl[(size_t)(BX + t2) * n + c0] = Cast<S>::of(o.F[5]);
           fl[(size_t)EN * n + c0] = Cast<S>::of(o.F[6]);
           fl[(size_t)(BX + d) * n + c0] = S(0);
-          Ap[d][c0] = o.ap;
-          Am[d][c0] = o.am;
-          Vt[d][(size_t)t1 * n + c0] = o.vt1;
-          Vt[d][(size_t)t2 * n + c0] = o.vt2;
+          if (uh) {
+            Ap[d][c0] = o.om;
+            Am[d][c0] = o.dl;
+            Dr[d][c0] = o.dr;
+            Vt[d][(size_t)t1 * n + c0] = o.wt1;
+            Vt[d][(size_t)t2 * n + c0] = o.wt2;
+          } else {
+            Ap[d][c0] = o.ap;
+            Am[d][c0] = o.am;
+            Vt[d][(size_t)t1 * n + c0] = o.vt1;
+            Vt[d][(size_t)t2 * n + c0] = o.vt2;
+          }
         }
     });
   }
@@ -546,12 +638,8 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
           };
           // a-faces touching the edge: cells c0 - e_b and c0
           const size_t ca = G.shift(i, j, k, b, -1);
-          const R apa = Max(Ap[a][ca], Ap[a][c0]);
-          const R ama = Max(Am[a][ca], Am[a][c0]);
           // b-faces touching the edge: cells c0 - e_a and c0
           const size_t cb = G.shift(i, j, k, a, -1);
-          const R apb = Max(Ap[b][cb], Ap[b][c0]);
-          const R amb = Max(Am[b][cb], Am[b][c0]);
           // W/E: on b-faces, v_a and B_b reconstructed along a
           R vW, vE, bW, bE;
           recon([&](size_t q) { return Vt[b][(size_t)a * n + q]; }, a, vW, vE);
@@ -560,7 +648,23 @@ int compute_rhs(const OCfg& cfg, const S* U, S* L) {
           R vS, vN, bS, bN;
           recon([&](size_t q) { return Vt[a][(size_t)b * n + q]; }, b, vS, vN);
           recon([&](size_t q) { return Cast<R>::of(F(BX + a)[q]); }, b, bS, bN);
-          Ed[c][c0] = Cast<S>::of(uct_emf<R>(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN));
+          if (uh) {
+            const R aa = R(0.5) * (Ap[a][ca] + Ap[a][c0]);
+            const R dla = R(0.5) * (Am[a][ca] + Am[a][c0]);
+            const R dra = R(0.5) * (Dr[a][ca] + Dr[a][c0]);
+            const R ab = R(0.5) * (Ap[b][cb] + Ap[b][c0]);
+            const R dlb = R(0.5) * (Am[b][cb] + Am[b][c0]);
+            const R drb = R(0.5) * (Dr[b][cb] + Dr[b][c0]);
+            Ed[c][c0] = Cast<S>::of(
+                uct_hlld_emf<R>(aa, dla, dra, vW, bW, vE, bE, ab, dlb, drb, vS, bS, vN, bN));
+          } else {
+            const R apa = Max(Ap[a][ca], Ap[a][c0]);
+            const R ama = Max(Am[a][ca], Am[a][c0]);
+            const R apb = Max(Ap[b][cb], Ap[b][c0]);
+            const R amb = Max(Am[b][cb], Am[b][c0]);
+            Ed[c][c0] =
+                Cast<S>::of(uct_emf<R>(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN));
+          }
         }
     });
   }
@@ -690,6 +794,186 @@ int cfl_dt(const OCfg& cfg, const double* U, double* dt_out) {
   return bad;
 }
 
+// ---------------------------------------------------------------------------
+// GLM divergence cleaning (Sec. 2.1 lists it beside CT as the control of div B;
+// Dedner et al. 2002) [reading: the mixed GLM form, with the energy equation
+// left as in Eq. (Energy)]. Nine cell-centred fields (rho, m, E, B, psi):
+//   dB/dt + div(vB - Bv) + grad psi = 0,
+//   dpsi/dt + c_h^2 div B = -(c_h^2 / c_p^2) psi,
+// the hyperbolic part in the finite-volume form of Eq. (FV) and the damping
+// applied after each full step as psi <- psi exp(-alpha c_h dt / Delta_min).
+// c_h = C Delta_min / dt: the largest speed the step's dt allows [reading];
+// alpha = 0.1 [reading].
+constexpr int NG = 9;
+enum { PSI = 8 };
+constexpr double kGlmAlpha = 0.1;
+
+// The (B_n, psi) subsystem decouples from the rest at a face; its exact
+// Riemann solution gives the interface values bn_s, psi_s, whose fluxes are
+// psi_s (for B_n) and c_h^2 bn_s (for psi); the rest of the face is the MHD
+// Riemann problem with the normal field bn_s on both sides.
+template <class R>
+void glm_face(int solver, R g, const R wl[7], const R wr[7], R bnl, R bnr, R psil, R psir, R ch,
+              R F[9]) {
+  const R bn_s = R(0.5) * (bnl + bnr) - (psir - psil) / (R(2) * ch);
+  const R psi_s = R(0.5) * (psil + psir) - R(0.5) * ch * (bnr - bnl);
+  RSOut<R> o;
+  riemann<R>(solver, g, wl, wr, bn_s, o);
+  for (int q = 0; q < 7; ++q) F[q] = o.F[q];
+  F[7] = psi_s;
+  F[8] = ch * ch * bn_s;
+}
+
+template <class S, class R>
+int compute_rhs_glm(const OCfg& cfg, const S* U, S* L, double ch) {
+  const Grid G(cfg);
+  const size_t n = G.ncell;
+  const int dim = G.dim;
+  const S gamma = S(cfg.gamma);
+  const R gR = Cast<R>::of(S(cfg.gamma));
+  auto F = [&](int f) { return U + (size_t)f * n; };
+  // primitives (rho, v, p, B, psi), FP64
+  std::vector<S> V((size_t)NG * n);
+  auto Vf = [&](int f) { return V.data() + (size_t)f * n; };
+  std::vector<int> badk((size_t)G.nz * G.ny, 0);
+  par_rows(G, cfg.nthreads, [&](int j, int k) {
+      for (int i = 0; i < G.nx; ++i) {
+        const size_t c = G.at(i, j, k);
+        const S rho = F(RHO)[c];
+        const S vx = F(MX)[c] / rho, vy = F(MY)[c] / rho, vz = F(MZ)[c] / rho;
+        const S kin = S(0.5) * (F(MX)[c] * vx + F(MY)[c] * vy + F(MZ)[c] * vz);
+        const S mag = S(0.5) * (F(BX)[c] * F(BX)[c] + F(BY)[c] * F(BY)[c] + F(BZ)[c] * F(BZ)[c]);
+        const S p = (gamma - S(1)) * (F(EN)[c] - kin - mag);
+        Vf(VRHO)[c] = rho; Vf(VVX)[c] = vx; Vf(VVY)[c] = vy; Vf(VVZ)[c] = vz; Vf(VPR)[c] = p;
+        Vf(VBX)[c] = F(BX)[c]; Vf(VBY)[c] = F(BY)[c]; Vf(VBZ)[c] = F(BZ)[c];
+        Vf(PSI)[c] = F(PSI)[c];
+        if (!(val(rho) > 0.0) || !(val(p) > 0.0) || !Finite(p) || !Finite(rho) ||
+            !Finite(vx) || !Finite(vy) || !Finite(vz))
+          badk[(size_t)k * G.ny + j] = 1;
+      }
+  });
+  int bad = 0;
+  for (int r : badk) bad |= r;
+  // fluxes of the nine fields through every lower face, global components
+  std::vector<S> Fl[3];
+  const R chR = Cast<R>::of(S(ch));
+  for (int d = 0; d < dim; ++d) {
+    Fl[d].assign((size_t)NG * n, S(0));
+    const int t1 = t1_of(d), t2 = t2_of(d);
+    // face frame (rho, v_n, v_t1, v_t2, B_t1, B_t2, p), then B_n and psi
+    const int slot[9] = {VRHO, VVX + d, VVX + t1, VVX + t2, VBX + t1, VBX + t2, VPR, VBX + d, PSI};
+    par_rows(G, cfg.nthreads, [&](int j, int k) {
+        for (int i = 0; i < G.nx; ++i) {
+          const size_t cm2 = G.shift(i, j, k, d, -2), cm1 = G.shift(i, j, k, d, -1);
+          const size_t c0 = G.at(i, j, k), cp1 = G.shift(i, j, k, d, +1);
+          const size_t cm3 = G.shift(i, j, k, d, -3), cp2 = G.shift(i, j, k, d, +2);
+          R wl[9], wr[9];
+          for (int q = 0; q < 9; ++q) {
+            const S* P = Vf(slot[q]);
+            const R a = Cast<R>::of(P[cm2]), b = Cast<R>::of(P[cm1]);
+            const R c = Cast<R>::of(P[c0]), e = Cast<R>::of(P[cp1]);
+            if (cfg.limiter == 2) {
+              const R z = Cast<R>::of(P[cm3]), f = Cast<R>::of(P[cp2]);
+              wl[q] = wenoz_upper(z, a, b, c, e);
+              wr[q] = wenoz_upper(f, e, c, b, a);
+            } else {
+              wl[q] = b + R(0.5) * limited_slope(cfg.limiter, b - a, c - b);
+              wr[q] = c - R(0.5) * limited_slope(cfg.limiter, c - b, e - c);
+            }
+          }
+          R Ff[9];
+          glm_face<R>(cfg.riemann, gR, wl, wr, wl[7], wr[7], wl[8], wr[8], chR, Ff);
+          S* fl = Fl[d].data();
+          fl[(size_t)RHO * n + c0] = Cast<S>::of(Ff[0]);
+          fl[(size_t)(MX + d) * n + c0] = Cast<S>::of(Ff[1]);
+          fl[(size_t)(MX + t1) * n + c0] = Cast<S>::of(Ff[2]);
+          fl[(size_t)(MX + t2) * n + c0] = Cast<S>::of(Ff[3]);
+          fl[(size_t)(BX + t1) * n + c0] = Cast<S>::of(Ff[4]);
+          fl[(size_t)(BX + t2) * n + c0] = Cast<S>::of(Ff[5]);
+          fl[(size_t)EN * n + c0] = Cast<S>::of(Ff[6]);
+          fl[(size_t)(BX + d) * n + c0] = Cast<S>::of(Ff[7]);
+          fl[(size_t)PSI * n + c0] = Cast<S>::of(Ff[8]);
+        }
+    });
+  }
+  // flux divergence of all nine fields
+  par_rows(G, cfg.nthreads, [&](int j, int k) {
+      for (int i = 0; i < G.nx; ++i) {
+        const size_t c0 = G.at(i, j, k);
+        const size_t xp = G.at(i + 1, j, k), yp = G.at(i, j + 1, k), zp = G.at(i, j, k + 1);
+        for (int q = 0; q < NG; ++q) {
+          const S* fx = Fl[0].data() + (size_t)q * n;
+          const S* fy = Fl[1].data() + (size_t)q * n;
+          S acc = (fx[xp] - fx[c0]) / S(G.dx) + (fy[yp] - fy[c0]) / S(G.dy);
+          if (dim == 3) {
+            const S* fz = Fl[2].data() + (size_t)q * n;
+            acc = acc + (fz[zp] - fz[c0]) / S(G.dz);
+          }
+          L[(size_t)q * n + c0] = -acc;
+        }
+      }
+  });
+  return bad;
+}
+
+double glm_dmin(const Grid& G) {
+  double m = std::min(G.dx, G.dy);
+  return G.dim == 3 ? std::min(m, G.dz) : m;
+}
+
+// One step of the configured integrator on the nine GLM fields, then the damping.
+int glm_step(const OCfg& cfg, double* U, double dt) {
+  const Grid G(cfg);
+  const size_t N = (size_t)NG * G.ncell;
+  const double dmin = glm_dmin(G);
+  const double ch = cfg.cfl * dmin / dt;
+  auto rhs = [&](const double* u, double* l) {
+    if (cfg.precision == 1) return compute_rhs_glm<double, float>(cfg, u, l, ch);
+    return compute_rhs_glm<double, double>(cfg, u, l, ch);
+  };
+  std::vector<double> L(N), U1(N);
+  int bad = rhs(U, L.data());
+  for (size_t q = 0; q < N; ++q) U1[q] = U[q] + dt * L[q];
+  bad |= rhs(U1.data(), L.data());
+  if (cfg.integrator == 1) {
+    std::vector<double> U2(N);
+    for (size_t q = 0; q < N; ++q) U2[q] = (3.0 * U[q] + (U1[q] + dt * L[q])) / 4.0;
+    bad |= rhs(U2.data(), L.data());
+    for (size_t q = 0; q < N; ++q) U[q] = (U[q] + 2.0 * (U2[q] + dt * L[q])) / 3.0;
+  } else {
+    for (size_t q = 0; q < N; ++q) U[q] = 0.5 * (U[q] + (U1[q] + dt * L[q]));
+  }
+  const double decay = std::exp(-kGlmAlpha * ch * dt / dmin);
+  double* psi = U + (size_t)PSI * G.ncell;
+  for (size_t c = 0; c < G.ncell; ++c) psi[c] = psi[c] * decay;
+  return bad;
+}
+
+// CFL time step of a GLM state (cell-centred B), same formula as cfl_dt.
+int glm_cfl_dt(const OCfg& cfg, const double* U, double* dt_out) {
+  const Grid G(cfg);
+  const size_t n = G.ncell;
+  const double g = cfg.gamma;
+  double m = INFINITY;
+  int bad = 0;
+  for (size_t c = 0; c < n; ++c) {
+    const double rho = U[c];
+    const double B[3] = {U[BX * n + c], U[BY * n + c], U[BZ * n + c]};
+    const double v[3] = {U[MX * n + c] / rho, U[MY * n + c] / rho, U[MZ * n + c] / rho};
+    const double kin = 0.5 * (U[MX * n + c] * v[0] + U[MY * n + c] * v[1] + U[MZ * n + c] * v[2]);
+    const double mag = 0.5 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    const double p = (g - 1.0) * (U[EN * n + c] - kin - mag);
+    if (!(rho > 0.0) || !(p > 0.0) || !std::isfinite(p)) bad = 1;
+    for (int d = 0; d < G.dim; ++d) {
+      const double cf = fast_speed<double>(g, rho, p, B[d], B[(d + 1) % 3], B[(d + 2) % 3]);
+      const double t = G.delta(d) / (std::fabs(v[d]) + cf);
+      if (t < m) m = t;
+    }
+  }
+  *dt_out = cfg.cfl * m;
+  return bad;
+}
+
 bool cfg_ok(const OCfg* c) {
   if (!c) return false;
   if (c->dim != 2 && c->dim != 3) return false;
@@ -700,6 +984,7 @@ bool cfg_ok(const OCfg* c) {
   if (c->limiter < 0 || c->limiter > 2 || c->riemann < 0 || c->riemann > 1) return false;
   if (c->precision < 0 || c->precision > 1) return false;
   if (c->integrator < 0 || c->integrator > 1) return false;
+  if (c->emf < 0 || c->emf > 1) return false;
   if (!(c->xmax > c->xmin) || !(c->ymax > c->ymin) || !(c->zmax > c->zmin)) return false;
   return true;
 }
@@ -755,6 +1040,47 @@ int oracle_run_dts(const OCfg* cfg, double* U, int nsteps, const double* dts) {
     });
   }
   return bad ? -4 : 0;
+}
+
+// GLM divergence cleaning: nine cell-centred fields (rho, m, E, B, psi).
+int oracle_glm_dt(const OCfg* cfg, const double* U, double* dt) {
+  if (!cfg_ok(cfg) || !U || !dt) return -1;
+  return glm_cfl_dt(*cfg, U, dt) ? -4 : 0;
+}
+
+int oracle_glm_run_dts(const OCfg* cfg, double* U, int nsteps, const double* dts) {
+  if (!cfg_ok(cfg) || !U || nsteps < 0 || !dts) return -1;
+  int bad = 0;
+  for (int s = 0; s < nsteps; ++s) bad |= glm_step(*cfg, U, dts[s]);
+  return bad ? -4 : 0;
+}
+
+int oracle_glm_run(const OCfg* cfg, double* U, int nsteps, double* dts) {
+  if (!cfg_ok(cfg) || !U || nsteps < 0) return -1;
+  int bad = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    double dt;
+    bad |= glm_cfl_dt(*cfg, U, &dt);
+    if (dts) dts[s] = dt;
+    bad |= glm_step(*cfg, U, dt);
+  }
+  return bad ? -4 : 0;
+}
+
+// Right-hand side of the GLM system for a given c_h (no damping).
+int oracle_glm_rhs(const OCfg* cfg, const double* U, double* L, double ch) {
+  if (!cfg_ok(cfg) || !U || !L || !(ch > 0.0)) return -1;
+  const int bad = cfg->precision == 1 ? compute_rhs_glm<double, float>(*cfg, U, L, ch)
+                                      : compute_rhs_glm<double, double>(*cfg, U, L, ch);
+  return bad ? -4 : 0;
+}
+
+// One GLM face: out[9] = fluxes of (rho, m_n, m_t1, m_t2, B_t1, B_t2, E, B_n, psi).
+int oracle_glm_face(int solver, double gamma, const double* wl, const double* wr, double bnl,
+                    double bnr, double psil, double psir, double ch, double* out) {
+  if (!wl || !wr || !out || !(gamma > 1.0) || !(ch > 0.0) || solver < 0 || solver > 1) return -1;
+  glm_face<double>(solver, gamma, wl, wr, bnl, bnr, psil, psir, ch, out);
+  return 0;
 }
 
 // Forward-mode tangent of one step (FP64 only): on return U holds the new
@@ -846,15 +1172,17 @@ int oracle_riemann(int solver, int precision, double gamma, const double* wl,
     float l[7], r[7];
     for (int q = 0; q < 7; ++q) { l[q] = (float)wl[q]; r[q] = (float)wr[q]; }
     RSOut<float> o;
-    riemann<float>(solver, (float)gamma, l, r, (float)bn, o);
+    riemann<float>(solver, (float)gamma, l, r, (float)bn, o, true);
     for (int q = 0; q < 7; ++q) out[q] = o.F[q];
     out[7] = o.ap; out[8] = o.am; out[9] = o.vt1; out[10] = o.vt2;
+    out[11] = o.om; out[12] = o.dl; out[13] = o.dr; out[14] = o.wt1; out[15] = o.wt2;
     return 0;
   }
   RSOut<double> o;
-  riemann<double>(solver, gamma, wl, wr, bn, o);
+  riemann<double>(solver, gamma, wl, wr, bn, o, true);
   for (int q = 0; q < 7; ++q) out[q] = o.F[q];
   out[7] = o.ap; out[8] = o.am; out[9] = o.vt1; out[10] = o.vt2;
+  out[11] = o.om; out[12] = o.dl; out[13] = o.dr; out[14] = o.wt1; out[15] = o.wt2;
   return 0;
 }
 

@@ -104,6 +104,8 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr size_t kCtl = 256;      // control block: [0] dt (double), [8] flag (int)
 constexpr int kCflBlocks = 2048;  // CFL partials (grid-stride reduction)
+// GLM damping rate alpha (psi <- psi exp(-alpha c_h dt / Delta_min) per step)
+constexpr double kGlmAlpha = 0.1;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -120,6 +122,9 @@ bool cfg_valid(const mhd_config* c) {
   if (c->limiter == MHD_LIM_WENOZ && c->precision != MHD_PREC_FP64) return false;
   if (c->precision < 0 || c->precision > 1) return false;
   if (c->integrator != MHD_SSP_RK2 && c->integrator != MHD_SSP_RK3) return false;
+  if (c->emf != MHD_EMF_UCT_HLL && c->emf != MHD_EMF_UCT_HLLD) return false;
+  if (c->divb != MHD_DIVB_CT && c->divb != MHD_DIVB_GLM) return false;
+  if (c->divb == MHD_DIVB_GLM && c->emf != MHD_EMF_UCT_HLL) return false;  // no EMF in GLM
   // 64-bit cell count; per-axis sizes bounded so index arithmetic stays in int
   const double cells = (double)c->nx * c->ny * c->nz;
   if (cells > 4.0e9) return false;
@@ -146,11 +151,20 @@ mhd::StageArgs stage_args(mhd_ctx* ctx, void* ws, hipStream_t s) {
   a.limiter = ctx->cfg.limiter;
   a.riemann = ctx->cfg.riemann;
   a.precision = ctx->cfg.precision;
+  a.emf = ctx->cfg.emf;
   a.g = ctx->g;
   a.FW = reinterpret_cast<double*>(base(ws) + ctx->off_fw);
   a.EW = reinterpret_cast<double*>(base(ws) + ctx->off_ew);
-  a.PW = ctx->cfg.limiter == MHD_LIM_WENOZ
+  a.glm = ctx->cfg.divb == MHD_DIVB_GLM;
+  a.PW = (ctx->cfg.limiter == MHD_LIM_WENOZ || a.glm)
              ? reinterpret_cast<double*>(base(ws) + ctx->off_pw) : nullptr;
+  if (a.glm) {
+    // c_h = C Delta_min / dt; the damping per step exp(-alpha c_h dt / Delta_min)
+    a.glm_dmin = std::min(ctx->g.dx, ctx->g.dy);
+    if (ctx->cfg.dim == 3) a.glm_dmin = std::min(a.glm_dmin, ctx->g.dz);
+    a.cfl = ctx->cfg.cfl;
+    a.glm_decay = std::exp(-kGlmAlpha * ctx->cfg.cfl);
+  }
   a.flag = ws_flag(ws);
   a.stream = s;
   a.timer = ctx->timer;
@@ -203,6 +217,21 @@ mhd_status run_step(mhd_ctx* ctx, double* U, double dt, const double* dtp, void*
 }
 
 mhd_status cfl_to(mhd_ctx* ctx, const double* U, void* ws, double* dt_dev, hipStream_t s) {
+  if (ctx->cfg.divb == MHD_DIVB_GLM) {  // through the GLM primitive kernel
+    mhd::CflArgs a{};
+    a.dim = ctx->cfg.dim;
+    a.g = ctx->g;
+    a.U = U;
+    a.partial = reinterpret_cast<double*>(base(ws) + ctx->off_partial);
+    a.cfl = ctx->cfg.cfl;
+    a.dt_out = dt_dev;
+    a.flag = ws_flag(ws);
+    a.stream = s;
+    a.timer = ctx->timer;
+    hipError_t e = mhd::launch_glm_cfl(a, reinterpret_cast<double*>(base(ws) + ctx->off_pw));
+    if (e != hipSuccess) return device_fail(ctx, e, "cfl");
+    return MHD_OK;
+  }
   mhd::CflArgs a{};
   a.dim = ctx->cfg.dim;
   a.g = ctx->g;
@@ -253,24 +282,27 @@ mhd_status mhd_init(const mhd_config* cfg, mhd_ctx** out) {
   c->g.dz = (cfg->zmax - cfg->zmin) / cfg->nz;
   c->g.gamma = cfg->gamma;
   const size_t n = (size_t)c->g.n;
+  const bool glm = cfg->divb == MHD_DIVB_GLM;
+  const size_t nf = glm ? 9 : 8;  // stored fields
   c->cfl_blocks = kCflBlocks;
   // CFL partials: of k_cfl, or (3D) one per face (WENO-Z: primitive) workgroup
-  // of the fused step
+  // of the fused step; GLM: one per primitive workgroup in 2D and 3D
   size_t npart = kCflBlocks;
-  if (cfg->dim == 3) npart = std::max(npart, mhd::stage_cfl_blocks(c->g, cfg->limiter));
+  if (cfg->dim == 3 || glm)
+    npart = std::max(npart, mhd::stage_cfl_blocks(c->g, cfg->limiter, glm));
   size_t off = kCtl;
   c->off_partial = off;
   off = align_up(off + sizeof(double) * npart);
   c->off_u1 = off;
-  off = align_up(off + sizeof(double) * 8 * n);
-  c->off_fw = off;
-  off = align_up(off + sizeof(double) * (size_t)cfg->dim * mhd::NSLOT * n);
+  off = align_up(off + sizeof(double) * nf * n);
+  c->off_fw = off;  // face records (CT) or the nine face fluxes per direction (GLM)
+  off = align_up(off + sizeof(double) * (size_t)cfg->dim * (glm ? 9 : mhd::NSLOT) * n);
   c->off_ew = off;
-  off = align_up(off + sizeof(double) * 3 * n);
+  if (!glm) off = align_up(off + sizeof(double) * 3 * n);
   c->off_u2 = off;  // SSP-RK3: the second-stage state
-  if (cfg->integrator == MHD_SSP_RK3) off = align_up(off + sizeof(double) * 8 * n);
-  c->off_pw = off;  // WENO-Z: the primitives of every cell
-  if (cfg->limiter == MHD_LIM_WENOZ) off = align_up(off + sizeof(double) * 8 * n);
+  if (cfg->integrator == MHD_SSP_RK3) off = align_up(off + sizeof(double) * nf * n);
+  c->off_pw = off;  // WENO-Z and GLM: the primitives of every cell
+  if (cfg->limiter == MHD_LIM_WENOZ || glm) off = align_up(off + sizeof(double) * nf * n);
   c->bytes_fwd = off;
   c->off_adj = off;
   c->bytes_adj = off + mhd::adjoint_workspace_bytes(cfg->dim, n, cfg->integrator);
@@ -302,6 +334,7 @@ mhd_status mhd_dt_device_noalloc(mhd_ctx* ctx, const double* U, double* dt_dev,
                                  int32_t* flag_dev, void* stream) {
   if (!ctx) return MHD_ERR_INVALID;
   if (!U || !dt_dev) return MHD_ERR_INVALID;
+  if (ctx->cfg.divb == MHD_DIVB_GLM) return MHD_ERR_UNSUPPORTED;
   mhd::CflArgs a{};
   a.dim = ctx->cfg.dim;
   a.g = ctx->g;
@@ -356,7 +389,8 @@ mhd_status mhd_step_cfl(mhd_ctx* ctx, double* U, double* dt_dev, void* ws, size_
   if (!U || !dt_dev) return MHD_ERR_INVALID;
   if (!ws_ok(ctx, ws, ws_bytes, false)) return MHD_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (ctx->cfg.dim == 3) return run_step(ctx, U, 0.0, dt_dev, ws, s, dt_dev);
+  if (ctx->cfg.dim == 3 || ctx->cfg.divb == MHD_DIVB_GLM)
+    return run_step(ctx, U, 0.0, dt_dev, ws, s, dt_dev);
   mhd_status st = cfl_to(ctx, U, ws, dt_dev, s);  // 2D: the separate CFL pass
   if (st != MHD_OK) return st;
   return run_step(ctx, U, 0.0, dt_dev, ws, s);
@@ -366,6 +400,7 @@ mhd_status mhd_rhs(mhd_ctx* ctx, const double* U, double* L, void* ws, size_t ws
                    void* stream) {
   if (!ctx) return MHD_ERR_INVALID;
   if (!U || !L || U == L) return MHD_ERR_INVALID;
+  if (ctx->cfg.divb == MHD_DIVB_GLM) return MHD_ERR_UNSUPPORTED;  // c_h needs the step's dt
   if (!ws_ok(ctx, ws, ws_bytes, false)) return MHD_ERR_WORKSPACE;
   mhd::StageArgs a = stage_args(ctx, ws, static_cast<hipStream_t>(stream));
   a.stage = 0;
@@ -385,7 +420,8 @@ static mhd_status adjoint_impl(mhd_ctx* ctx, const double* U_n, double dt, const
   if (!ctx) return MHD_ERR_INVALID;
   if (!U_n || !Ubar_np1 || !Ubar_n || !(dt > 0.0) || !std::isfinite(dt)) return MHD_ERR_INVALID;
   if (Ubar_n == Ubar_np1 || Ubar_n == U_n) return MHD_ERR_INVALID;
-  if (ctx->cfg.precision != MHD_PREC_FP64 || ctx->cfg.limiter == MHD_LIM_WENOZ)
+  if (ctx->cfg.precision != MHD_PREC_FP64 || ctx->cfg.limiter == MHD_LIM_WENOZ ||
+      ctx->cfg.emf != MHD_EMF_UCT_HLL || ctx->cfg.divb != MHD_DIVB_CT)
     return MHD_ERR_UNSUPPORTED;
   if (!ws_ok(ctx, ws, ws_bytes, true)) return MHD_ERR_WORKSPACE;
   mhd::AdjointArgs a{};

@@ -29,9 +29,11 @@ enum : int { F_RHO = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_EN = 4, F_BX = 5, F_BY =
 
 // Per-face record slots (one array of N values per slot, per direction):
 // fluxes of the cell-averaged fields, then the quantities the edge EMF needs.
+// With the UCT-HLLD average, S_AP holds its weight om, S_AM its diffusion
+// coefficient d^L and S_DR d^R, and S_V1/S_V2 the om-weighted velocities.
 enum : int {
   S_RHO = 0, S_MX = 1, S_MY = 2, S_MZ = 3, S_EN = 4, S_BZ = 5,  // S_BZ: 2D only
-  S_AP = 6, S_AM = 7, S_V1 = 8, S_V2 = 9, NSLOT = 10
+  S_AP = 6, S_AM = 7, S_V1 = 8, S_V2 = 9, S_DR = 10, NSLOT = 11
 };
 
 struct Geom {
@@ -157,7 +159,8 @@ template <class R> struct FState { R w[7]; };
 template <class R> struct RiemannOut {
   R f[7];        // flux of (rho, m_n, m_t1, m_t2, B_t1, B_t2, E)
   R ap, am;      // max(0, S_R), max(0, -S_L)
-  R v1, v2;      // HLL-weighted transverse velocities
+  R v1, v2;      // HLL-weighted transverse velocities (EM 1: om-weighted)
+  R om, dl, dr;  // EM 1: UCT-HLLD weight of the left state, diffusion coefficients
 };
 
 // Fast magnetosonic speed along the normal.
@@ -224,7 +227,22 @@ struct RiemannTape {
 // of Miyoshi & Kusano (contact S_M, Alfven fronts S*_L, S*_R); when
 // rho (S-u)(S-S_M) - bn^2 vanishes (relative DegenerateTol) the tangential
 // fields of that side's star state are left unchanged. Region ties go left.
-template <int RS, class R, class T>
+//
+// EM 1 also gives the coefficients of the UCT-HLLD edge average. At the wave
+// structure of the face the flux of each transverse field component is
+// linear in the outer transverse fields and velocities,
+//   F[B_t] = chiL B_t^L + chiR B_t^R - bn (om v_t^L + (1 - om) v_t^R);
+// the EMF takes om, 1 - om as the weights of v_n B_t on either side,
+// d^L = chiL - om u_L and d^R = (1 - om) u_R - chiR as its diffusion
+// coefficients, and v1, v2 become the om-weighted velocities. Per region
+// (B*_t = zeta B_t and v*_t = v_t - eta B_t on each side; w = 1/(sql + sqr)):
+//   F_L, F*_L:  om = 1, chiL = u_L + S_L (zeta_L - 1), chiR = 0;
+//   F**_L:      om = 1 + S*_L w sql sqr / |bn|,
+//               chiL = u_L + S_L (zeta_L - 1) + S*_L (w (sqr zeta_L + s sql sqr eta_L) - zeta_L),
+//               chiR = S*_L w (sql zeta_R - s sql sqr eta_R), s = sign(bn);
+//   F**_R, F*_R, F_R: the mirror images. For HLL: om = alpha+/(alpha+ + alpha-),
+//   d^L = d^R = alpha+ alpha-/(alpha+ + alpha-).
+template <int RS, class R, class T, int EM = 0>
 __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn,
                                              RiemannOut<R>& o, T& tp) {
   R ul[7], fl[7], ur[7], fr[7], ptl, ptr;
@@ -249,6 +267,11 @@ __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn
     tp.ptl = ptl; tp.ptr = ptr; tp.cl = cl; tp.cr = cr; tp.sl = sl; tp.sr = sr;
     tp.ap = o.ap; tp.am = o.am; tp.isum = isum; tp.v1 = o.v1; tp.v2 = o.v2;
   }
+  if (EM == 1 && RS == 1) {
+    o.om = o.ap * isum;
+    o.dl = o.ap * o.am * isum;
+    o.dr = o.dl;
+  }
   if (RS == 1) {
     if (sl >= R(0)) {
       if constexpr (T::on) tp.region = 0;
@@ -271,12 +294,14 @@ __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn
     if constexpr (T::on) tp.region = 0;
 #pragma unroll
     for (int q = 0; q < 7; ++q) o.f[q] = fl[q];
+    if (EM == 1) { o.om = R(1); o.dl = R(0); o.dr = R(0); o.v1 = wl[2]; o.v2 = wl[3]; }
     return;
   }
   if (sr < R(0)) {
     if constexpr (T::on) tp.region = 1;
 #pragma unroll
     for (int q = 0; q < 7; ++q) o.f[q] = fr[q];
+    if (EM == 1) { o.om = R(0); o.dl = R(0); o.dr = R(0); o.v1 = wr[2]; o.v2 = wr[3]; }
     return;
   }
   const R dl = sl - wl[1], dr = sr - wr[1];
@@ -291,6 +316,7 @@ __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn
 
   // star states, one side at a time: s = 0 left, 1 right
   R rs[2], vs[2], ws[2], b1s[2], b2s[2], es[2];
+  R zeta[2], eta[2];  // EM 1: B*_t = zeta B_t, v*_t = v_t - eta B_t
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const R* w = s ? wr : wl;
@@ -306,6 +332,8 @@ __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn
     const bool deg = abs_r(den) <= R(DegenerateTol<R>::value) * (abs_r(big) + bn2);
     if (deg) {
       vs[s] = w[2]; ws[s] = w[3]; b1s[s] = w[4]; b2s[s] = w[5];
+      zeta[s] = R(1);
+      eta[s] = R(0);
     } else {
       const R iden2 = rcp_r(den);
       const R fv = bn * (sm - w[1]) * iden2;
@@ -314,6 +342,8 @@ __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn
       const R fb = fma_r(m, d, -bn2) * iden2;
       b1s[s] = w[4] * fb;
       b2s[s] = w[5] * fb;
+      zeta[s] = fb;
+      eta[s] = fv;
       if constexpr (T::on) { tp.iden2[s] = iden2; tp.fv[s] = fv; tp.fb[s] = fb; }
     }
     const R vb = fma_r(w[3], w[5], fma_r(w[2], w[4], w[1] * bn));
@@ -333,6 +363,13 @@ __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn
 
   if (sls >= R(0)) {  // F*_L
     if constexpr (T::on) tp.region = 3;
+    if (EM == 1) {
+      o.om = R(1);
+      o.dl = sl * (zeta[0] - R(1));
+      o.dr = R(0);
+      o.v1 = wl[2];
+      o.v2 = wl[3];
+    }
     const R us[7] = {rs[0], rs[0] * sm, rs[0] * vs[0], rs[0] * ws[0], b1s[0], b2s[0], es[0]};
 #pragma unroll
     for (int q = 0; q < 7; ++q) o.f[q] = fma_r(sl, us[q] - ul[q], fl[q]);
@@ -349,6 +386,27 @@ __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn
   if constexpr (T::on) {
     tp.sgn = sgn; tp.isq = isq; tp.ssq = ssq; tp.vss = vss; tp.wss = wss; tp.b1ss = b1ss;
     tp.b2ss = b2ss; tp.vbss = vbss;
+  }
+  if (EM == 1) {
+    // F**_L or F**_R (|bn| > 0 there: S*_L < 0 <= S_M or S_M < 0 <= S*_R)
+    const R ww = isq * sql * sqr;
+    const R cl = fma_r(sgn * sql * sqr, eta[0], sqr * zeta[0]) * isq;  // B** per B_t^L
+    const R cr = fma_r(-sgn * sql * sqr, eta[1], sql * zeta[1]) * isq;  // B** per B_t^R
+    R chiL, chiR;
+    if (sm >= R(0)) {
+      o.om = R(1) - div_r(-sls * ww, abn);
+      chiL = fma_r(sls, cl - zeta[0], fma_r(sl, zeta[0] - R(1), wl[1]));
+      chiR = sls * cr;
+    } else {
+      o.om = div_r(srs * ww, abn);
+      chiR = fma_r(srs, cr - zeta[1], fma_r(sr, zeta[1] - R(1), wr[1]));
+      chiL = srs * cl;
+    }
+    const R omr = R(1) - o.om;
+    o.dl = fma_r(-o.om, wl[1], chiL);
+    o.dr = fma_r(omr, wr[1], -chiR);
+    o.v1 = fma_r(o.om, wl[2], omr * wr[2]);
+    o.v2 = fma_r(o.om, wl[3], omr * wr[3]);
   }
   if (sm >= R(0)) {  // F**_L
     const R ess = fma_r(-sgn * sql, fma_r(vs[0], b1s[0], ws[0] * b2s[0]) - vbss, es[0]);
@@ -375,14 +433,21 @@ __device__ __forceinline__ void riemann_core(R g, const R* wl, const R* wr, R bn
     return;
   }
   if constexpr (T::on) tp.region = 6;
+  if (EM == 1) {
+    o.om = R(0);
+    o.dl = R(0);
+    o.dr = -sr * (zeta[1] - R(1));
+    o.v1 = wr[2];
+    o.v2 = wr[3];
+  }
 #pragma unroll
   for (int q = 0; q < 7; ++q) o.f[q] = fma_r(sr, us[q] - ur[q], fr[q]);  // F*_R
 }
 
-template <int RS, class R>
+template <int RS, class R, int EM = 0>
 __device__ __forceinline__ void riemann(R g, const R* wl, const R* wr, R bn, RiemannOut<R>& o) {
   NoTape tp;
-  riemann_core<RS, R, NoTape>(g, wl, wr, bn, o, tp);
+  riemann_core<RS, R, NoTape, EM>(g, wl, wr, bn, o, tp);
 }
 
 // Upwind edge EMF for component c with cyclic pair (a, b); the exact value
@@ -394,6 +459,18 @@ __device__ __forceinline__ R uct(R apa, R ama, R vW, R bW, R vE, R bE,
                                  R apb, R amb, R vS, R bS, R vN, R bN) {
   const R ta = div_r(apa * vW * bW + ama * vE * bE - apa * ama * (bE - bW), apa + ama);
   const R tb = div_r(apb * vS * bS + amb * vN * bN - apb * amb * (bN - bS), apb + amb);
+  return tb - ta;
+}
+
+// UCT-HLLD edge EMF for component c with cyclic pair (a, b): the weights
+// (aa, 1 - aa) and diffusion coefficients dla, dra (averaged over the two
+// a-faces touching the edge) act on v_a B_b from the two b-faces
+// reconstructed along a (W, E); the b-bracket likewise.
+template <class R>
+__device__ __forceinline__ R uct_hlld(R aa, R dla, R dra, R vW, R bW, R vE, R bE, R ab, R dlb,
+                                      R drb, R vS, R bS, R vN, R bN) {
+  const R ta = aa * vW * bW + (R(1) - aa) * vE * bE - (dra * bE - dla * bW);
+  const R tb = ab * vS * bS + (R(1) - ab) * vN * bN - (drb * bN - dlb * bS);
   return tb - ta;
 }
 

@@ -122,6 +122,33 @@ __device__ __forceinline__ bool row_cell(const Geom& g, const TileGrid& tg, int&
   return i < g.nx && j < g.ny && k < g.nz;
 }
 
+// The record of a lower D-face: the fluxes of the cell fields (with B_z in
+// 2D), then the EMF inputs, alpha+- and the HLL-weighted velocities (EM 0),
+// or the UCT-HLLD weight, diffusion coefficients and weighted velocities
+// (EM 1). The normal-B flux is zero and the edge EMFs replace the B_t fluxes.
+template <int DIM, int D, int EM, class R>
+__device__ __forceinline__ void put_record(double* __restrict__ FW, int64_t n, int64_t c,
+                                           const RiemannOut<R>& o) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  R* fw = stored<R>(FW) + (int64_t)D * NSLOT * n + c;
+  fw[S_RHO * n] = o.f[0];
+  fw[(S_MX + D) * n] = o.f[1];
+  fw[(S_MX + T1) * n] = o.f[2];
+  fw[(S_MX + T2) * n] = o.f[3];
+  fw[S_EN * n] = o.f[6];
+  if (DIM == 2) fw[S_BZ * n] = (D == 0) ? o.f[5] : o.f[4];  // B_z is t2 of x, t1 of y
+  if (EM == 1) {
+    fw[S_AP * n] = o.om;
+    fw[S_AM * n] = o.dl;
+    fw[S_DR * n] = o.dr;
+  } else {
+    fw[S_AP * n] = o.ap;
+    fw[S_AM * n] = o.am;
+  }
+  fw[S_V1 * n] = o.v1;
+  fw[S_V2 * n] = o.v2;
+}
+
 // Upwind edge EMF from its inputs: alpha+- of the two a-faces touching the
 // edge (below the edge along B, then the cell's own), of the two b-faces
 // (below along A, then own); the face velocity v_A and the field b_B on the
@@ -141,9 +168,30 @@ __device__ __forceinline__ R emf_core(R apa_m, R apa_c, R ama_m, R ama_c, R apb_
   return uct<R>(apa, ama, vW, bW, vE, bE, apb, amb, vS, bS, vN, bN);
 }
 
+// UCT-HLLD edge EMF from its inputs: om, d^L, d^R of the two a-faces (below
+// the edge along B, then the cell's own) and of the two b-faces, averaged;
+// the reconstructed values as for emf_core.
+template <int LIM, class R>
+__device__ __forceinline__ R emf_core_hlld(R oma_m, R oma_c, R dla_m, R dla_c, R dra_m, R dra_c,
+                                           R omb_m, R omb_c, R dlb_m, R dlb_c, R drb_m, R drb_c,
+                                           const R* vbA, const R* bB, const R* vaB,
+                                           const R* bA) {
+  const R aa = R(0.5) * (oma_m + oma_c), dla = R(0.5) * (dla_m + dla_c);
+  const R dra = R(0.5) * (dra_m + dra_c);
+  const R ab = R(0.5) * (omb_m + omb_c), dlb = R(0.5) * (dlb_m + dlb_c);
+  const R drb = R(0.5) * (drb_m + drb_c);
+  R vW, vE, bW, bE, vS, vN, bS, bN;
+  edge_pair<LIM, R>(vbA[0], vbA[1], vbA[2], vbA[3], vW, vE);
+  edge_pair<LIM, R>(bB[0], bB[1], bB[2], bB[3], bW, bE);
+  edge_pair<LIM, R>(vaB[0], vaB[1], vaB[2], vaB[3], vS, vN);
+  edge_pair<LIM, R>(bA[0], bA[1], bA[2], bA[3], bS, bN);
+  return uct_hlld<R>(aa, dla, dra, vW, bW, vE, bE, ab, dlb, drb, vS, bS, vN, bN);
+}
+
 // Edge EMF of component C at cell (i,j,k): the edge at the lower A- and
-// lower B-position of the cell, (A, B) = (C+1, C+2) cyclic.
-template <int C, int LIM, class R>
+// lower B-position of the cell, (A, B) = (C+1, C+2) cyclic. EM 0: the
+// upwind average with the HLL bounds; EM 1: the UCT-HLLD average.
+template <int C, int LIM, class R, int EM = 0>
 __device__ __forceinline__ R emf_comp(const double* __restrict__ U,
                                       const double* __restrict__ FW, const Geom& g, int i, int j,
                                       int k, int64_t c) {
@@ -163,6 +211,12 @@ __device__ __forceinline__ R emf_comp(const double* __restrict__ U,
   const R wb[4] = {(R)bBf[a2], (R)bBf[cma], (R)bBf[c], (R)bBf[a1]};
   const R sv[4] = {vaB[b2], vaB[cmb], vaB[c], vaB[b1]};
   const R sb[4] = {(R)bAf[b2], (R)bAf[cmb], (R)bAf[c], (R)bAf[b1]};
+  if (EM == 1)
+    return emf_core_hlld<LIM, R>(fa[S_AP * n + cmb], fa[S_AP * n + c], fa[S_AM * n + cmb],
+                                 fa[S_AM * n + c], fa[S_DR * n + cmb], fa[S_DR * n + c],
+                                 fb[S_AP * n + cma], fb[S_AP * n + c], fb[S_AM * n + cma],
+                                 fb[S_AM * n + c], fb[S_DR * n + cma], fb[S_DR * n + c], wv, wb,
+                                 sv, sb);
   return emf_core<LIM, R>(fa[S_AP * n + cmb], fa[S_AP * n + c], fa[S_AM * n + cmb],
                           fa[S_AM * n + c], fb[S_AP * n + cma], fb[S_AP * n + c],
                           fb[S_AM * n + cma], fb[S_AM * n + c], wv, wb, sv, sb);
@@ -280,7 +334,7 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
   }
 }
 
-template <int DIM, int LIM, class R>
+template <int DIM, int LIM, class R, int EM>
 __global__ __launch_bounds__(RowTile::NT) void k_emf(const double* __restrict__ U,
                                                 const double* __restrict__ FW,
                                                 double* __restrict__ EW, Geom g, TileGrid tg) {
@@ -289,10 +343,10 @@ __global__ __launch_bounds__(RowTile::NT) void k_emf(const double* __restrict__ 
   const int64_t c = lin(g, i, j, k);
   R* ew = stored<R>(EW);
   if (DIM == 3) {
-    ew[c] = emf_comp<0, LIM, R>(U, FW, g, i, j, k, c);
-    ew[g.n + c] = emf_comp<1, LIM, R>(U, FW, g, i, j, k, c);
+    ew[c] = emf_comp<0, LIM, R, EM>(U, FW, g, i, j, k, c);
+    ew[g.n + c] = emf_comp<1, LIM, R, EM>(U, FW, g, i, j, k, c);
   }
-  ew[2 * g.n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
+  ew[2 * g.n + c] = emf_comp<2, LIM, R, EM>(U, FW, g, i, j, k, c);
 }
 
 // STAGE 0: out = L(U); 1: out = U + dt L(U); 2: out = (U0 + (U + dt L(U))) / 2
@@ -399,7 +453,7 @@ __device__ __forceinline__ void pslot_pos(int e, int& x, int& y, int& z) {
 }
 
 // One lower face of direction D of the tile cell (x,y,z) from LDS primitives.
-template <int DIM, int D, int LIM, int RS, class R>
+template <int DIM, int D, int LIM, int RS, class R, int EM>
 __device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM],
                                           const double* __restrict__ U, double* __restrict__ FW,
                                           const Geom& g, int x, int y, int z, int64_t c) {
@@ -421,25 +475,14 @@ __device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM],
   }
   const R bn = (R)U[(F_BX + D) * g.n + c];
   RiemannOut<R> o;
-  riemann<RS, R>((R)g.gamma, wl, wr, bn, o);
-  const int64_t n = g.n;
-  R* fw = stored<R>(FW) + (int64_t)D * NSLOT * n + c;
-  fw[S_RHO * n] = o.f[0];
-  fw[(S_MX + D) * n] = o.f[1];
-  fw[(S_MX + T1) * n] = o.f[2];
-  fw[(S_MX + T2) * n] = o.f[3];
-  fw[S_EN * n] = o.f[6];
-  if (DIM == 2) fw[S_BZ * n] = (D == 0) ? o.f[5] : o.f[4];  // B_z is t2 of x, t1 of y
-  fw[S_AP * n] = o.ap;
-  fw[S_AM * n] = o.am;
-  fw[S_V1 * n] = o.v1;
-  fw[S_V2 * n] = o.v2;
+  riemann<RS, R, EM>((R)g.gamma, wl, wr, bn, o);
+  put_record<DIM, D, EM, R>(FW, g.n, c, o);
 }
 
 // Face kernel: primitives of the tile and its cross halo are recovered once
 // (in FP64) into LDS, held in the reconstruction precision R, then each
 // thread solves the lower x/y(/z) faces of its cell.
-template <int DIM, int LIM, int RS, class R>
+template <int DIM, int LIM, int RS, class R, int EM>
 __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* __restrict__ U,
                                                         double* __restrict__ FW, Geom g,
                                                         TileGrid tg, int* __restrict__ flag) {
@@ -465,9 +508,9 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
   const int i = i0 + x, j = j0 + y, k = k0 + z;
   if (i >= g.nx || j >= g.ny || k >= g.nz) return;
   const int64_t c = lin(g, i, j, k);
-  tile_face<DIM, 0, LIM, RS, R>(sp, U, FW, g, x, y, z, c);
-  tile_face<DIM, 1, LIM, RS, R>(sp, U, FW, g, x, y, z, c);
-  if (DIM == 3) tile_face<DIM, 2, LIM, RS, R>(sp, U, FW, g, x, y, z, c);
+  tile_face<DIM, 0, LIM, RS, R, EM>(sp, U, FW, g, x, y, z, c);
+  tile_face<DIM, 1, LIM, RS, R, EM>(sp, U, FW, g, x, y, z, c);
+  if (DIM == 3) tile_face<DIM, 2, LIM, RS, R, EM>(sp, U, FW, g, x, y, z, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -551,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_prim_weno(const double* __restrict__
 // state is the upper value of cell -1 (cells -3..+1), the right state the
 // lower value of cell 0 (cells +2..-2 in reverse). One quantity at a time, so
 // that only its six values are live beside the reconstructed states.
-template <int DIM, int D, int RS>
+template <int DIM, int D, int RS, int EM>
 __device__ __forceinline__ void weno_face(const double* __restrict__ PW,
                                           const double* __restrict__ U, double* __restrict__ FW,
                                           const Geom& g, int i, int j, int k, int64_t c) {
@@ -576,34 +619,24 @@ __device__ __forceinline__ void weno_face(const double* __restrict__ PW,
     wr[q] = wenoz_upper(v[5], v[4], v[3], v[2], v[1]);
   }
   RiemannOut<double> o;
-  riemann<RS, double>(g.gamma, wl, wr, U[(F_BX + D) * n + c], o);
-  double* fw = FW + (int64_t)D * NSLOT * n + c;
-  fw[S_RHO * n] = o.f[0];
-  fw[(S_MX + D) * n] = o.f[1];
-  fw[(S_MX + T1) * n] = o.f[2];
-  fw[(S_MX + T2) * n] = o.f[3];
-  fw[S_EN * n] = o.f[6];
-  if (DIM == 2) fw[S_BZ * n] = (D == 0) ? o.f[5] : o.f[4];  // B_z is t2 of x, t1 of y
-  fw[S_AP * n] = o.ap;
-  fw[S_AM * n] = o.am;
-  fw[S_V1 * n] = o.v1;
-  fw[S_V2 * n] = o.v2;
+  riemann<RS, double, EM>(g.gamma, wl, wr, U[(F_BX + D) * n + c], o);
+  put_record<DIM, D, EM, double>(FW, n, c, o);
 }
 
 // Face kernel for WENO-Z (2D and 3D, FP64), one cell per thread, kBlock
 // consecutive cells per workgroup: its +-3-cell stencils are gathered from the
 // primitives PW through the caches rather than staged in LDS (a z-march ring
 // would need six planes and a 3-cell halo).
-template <int DIM, int RS>
+template <int DIM, int RS, int EM>
 __global__ __launch_bounds__(kBlock) void k_faces_weno(const double* __restrict__ PW,
                                                   const double* __restrict__ U,
                                                   double* __restrict__ FW, Geom g) {
   int i, j, k;
   int64_t c;
   if (!linear_cell(g, i, j, k, c)) return;
-  weno_face<DIM, 0, RS>(PW, U, FW, g, i, j, k, c);
-  weno_face<DIM, 1, RS>(PW, U, FW, g, i, j, k, c);
-  if (DIM == 3) weno_face<DIM, 2, RS>(PW, U, FW, g, i, j, k, c);
+  weno_face<DIM, 0, RS, EM>(PW, U, FW, g, i, j, k, c);
+  weno_face<DIM, 1, RS, EM>(PW, U, FW, g, i, j, k, c);
+  if (DIM == 3) weno_face<DIM, 2, RS, EM>(PW, U, FW, g, i, j, k, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -699,28 +732,17 @@ __device__ __forceinline__ void march_xy(int rp, int bp, int xx, int yy, int& o,
 }
 
 // Writes the nine records of a lower face from its reconstructed states.
-template <int D, int RS, class R>
+template <int D, int RS, class R, int EM>
 __device__ __forceinline__ void march_solve(const R* wl, const R* wr, R bn,
                                             double* __restrict__ FW, const Geom& g, int64_t c) {
-  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   RiemannOut<R> o;
-  riemann<RS, R>((R)g.gamma, wl, wr, bn, o);
-  const int64_t n = g.n;
-  R* fw = stored<R>(FW) + (int64_t)D * NSLOT * n + c;
-  fw[S_RHO * n] = o.f[0];
-  fw[(S_MX + D) * n] = o.f[1];
-  fw[(S_MX + T1) * n] = o.f[2];
-  fw[(S_MX + T2) * n] = o.f[3];
-  fw[S_EN * n] = o.f[6];
-  fw[S_AP * n] = o.ap;
-  fw[S_AM * n] = o.am;
-  fw[S_V1 * n] = o.v1;
-  fw[S_V2 * n] = o.v2;
+  riemann<RS, R, EM>((R)g.gamma, wl, wr, bn, o);
+  put_record<3, D, EM, R>(FW, g.n, c, o);
 }
 
 // Lower x (D = 0) or y (D = 1) face of a cell of plane k: PLM over the four
 // stencil cells (offsets o*, strides s*, B_z offsets b*), then the solver.
-template <int D, int LIM, int RS, class R>
+template <int D, int LIM, int RS, class R, int EM>
 __device__ __forceinline__ void march_face_xy(const R* lds, const int* o, const int* st,
                                               const int* ob, R bn,
                                               double* __restrict__ FW, const Geom& g, int64_t c) {
@@ -736,13 +758,13 @@ __device__ __forceinline__ void march_face_xy(const R* lds, const int* o, const 
     wl[q] = fma_r(R(0.5), plm_slope<LIM, R>(v[1] - v[0], v[2] - v[1]), v[1]);
     wr[q] = fma_r(R(-0.5), plm_slope<LIM, R>(v[2] - v[1], v[3] - v[2]), v[2]);
   }
-  march_solve<D, RS, R>(wl, wr, bn, FW, g, c);
+  march_solve<D, RS, R, EM>(wl, wr, bn, FW, g, c);
 }
 
 // cflp != nullptr: also the CFL bound of the state, reduced over the cells
 // of this workgroup's column and run (each cell is the own cell of exactly
 // one workgroup and plane) into cflp[blockIdx.x]; k_cfl_final finishes it.
-template <int LIM, int RS, class R>
+template <int LIM, int RS, class R, int EM>
 __global__ __launch_bounds__(kBlock)
 void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g, MarchGrid mg,
                    int* __restrict__ flag, double* __restrict__ cflp) {
@@ -823,11 +845,11 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
       march_xy(r0, b0, x - 1, y, o[1], st[1], ob[1]);
       march_xy(r0, b0, x, y, o[2], st[2], ob[2]);
       march_xy(r0, b0, x + 1, y, o[3], st[3], ob[3]);
-      march_face_xy<0, LIM, RS, R>(lds, o, st, ob, (R)bnx, FW, g, c);
+      march_face_xy<0, LIM, RS, R, EM>(lds, o, st, ob, (R)bnx, FW, g, c);
       march_xy(r0, b0, x, y - 2, o[0], st[0], ob[0]);
       march_xy(r0, b0, x, y - 1, o[1], st[1], ob[1]);
       march_xy(r0, b0, x, y + 1, o[3], st[3], ob[3]);
-      march_face_xy<1, LIM, RS, R>(lds, o, st, ob, (R)bny, FW, g, c);
+      march_face_xy<1, LIM, RS, R, EM>(lds, o, st, ob, (R)bny, FW, g, c);
       // z face: left state carried from the plane below; the slope of cell k
       // gives the right state and the next plane's left state
       R wl[7], wr[7];
@@ -842,7 +864,7 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
         wr[q] = fma_r(R(-0.5), dlt, bb);
         zl[q] = fma_r(R(0.5), dlt, bb);
       }
-      march_solve<2, RS, R>(wl, wr, (R)bnz, FW, g, c);
+      march_solve<2, RS, R, EM>(wl, wr, (R)bnz, FW, g, c);
     }
     if (more) {
       __syncthreads();  // plane k-1, B_z of plane k and the halo of plane k are free
@@ -925,6 +947,220 @@ __global__ __launch_bounds__(1024) void k_cfl_final(const double* __restrict__ p
   }
 }
 
+// ---------------------------------------------------------------------------
+// GLM divergence cleaning (Sec. 2.1 lists it beside CT; Dedner et al. 2002),
+// mixed form: nine cell-centred fields (rho, m_x, m_y, m_z, E, B_x, B_y, B_z,
+// psi), psi coupled to B by dB/dt + grad psi and dpsi/dt + c_h^2 div B, its
+// damping applied after each full step. One stage is three launches over
+// kBlock consecutive cells per workgroup: primitives of every cell (and the
+// CFL partials), faces (each cell's three lower faces from the primitives of
+// its stencil), update (flux divergence of the nine fields, RK combination,
+// the damping of psi in the last stage).
+constexpr int kGlmFields = 9;
+
+template <int DIM>
+__device__ __forceinline__ double cfl_bound_dim(const Geom& g, const double* W, double m) {
+  const double dd[3] = {g.dx, g.dy, g.dz};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double cf = cfast<double>(g.gamma, W[0], W[4], W[5 + d], W[5 + (d + 1) % 3],
+                                    W[5 + (d + 2) % 3]);
+    const double t = dd[d] / (__builtin_fabs(W[1 + d]) + cf);
+    m = (t < m) ? t : m;
+  }
+  return m;
+}
+
+// Primitives (rho, v_x, v_y, v_z, p, B_x, B_y, B_z, psi) of every cell into
+// PW[9][n] (FP64; the field is already cell-centred), the workgroup's CFL
+// partial into cflp[blockIdx.x] (nullable).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_glm_prim(const double* __restrict__ U,
+                                                double* __restrict__ PW, Geom g,
+                                                int* __restrict__ flag,
+                                                double* __restrict__ cflp) {
+  int i, j, k;
+  int64_t c;
+  const bool inside = linear_cell(g, i, j, k, c);
+  double cmin = __builtin_inf();
+  if (inside) {
+    const int64_t n = g.n;
+    const double rho = U[c];
+    const double mx = U[n + c], my = U[2 * n + c], mz = U[3 * n + c], en = U[4 * n + c];
+    const double bx = U[5 * n + c], by = U[6 * n + c], bz = U[7 * n + c];
+    const double irho = 1.0 / rho;
+    const double vx = mx * irho, vy = my * irho, vz = mz * irho;
+    const double kin = 0.5 * fma_r(mz, vz, fma_r(my, vy, mx * vx));
+    const double mag = 0.5 * fma_r(bz, bz, fma_r(by, by, bx * bx));
+    const double p = (g.gamma - 1.0) * (en - kin - mag);
+    const double V[9] = {rho, vx, vy, vz, p, bx, by, bz, U[8 * n + c]};
+#pragma unroll
+    for (int q = 0; q < kGlmFields; ++q) PW[q * n + c] = V[q];
+    const bool ok = (rho > 0.0) && (p > 0.0) && __builtin_isfinite(p) &&
+                    __builtin_isfinite(vx) && __builtin_isfinite(vy) && __builtin_isfinite(vz);
+    if (!ok) atomicOr(flag, 1);
+    if (cflp) cmin = cfl_bound_dim<DIM>(g, V, cmin);
+  }
+  if (cflp) workgroup_min_store(cmin, cflp + blockIdx.x);
+}
+
+// Lower D-face of cell (i,j,k): the nine quantities reconstructed from the
+// primitives along D (PLM over offsets -2..+1, or WENO-Z over -3..+2), then
+// the (B_n, psi) subsystem's exact interface values
+//   bn* = (bn_L + bn_R)/2 - (psi_R - psi_L)/(2 c_h),
+//   psi* = (psi_L + psi_R)/2 - c_h (bn_R - bn_L)/2,
+// the MHD Riemann flux with the normal field bn*, and the fluxes psi* of B_n
+// and c_h^2 bn* of psi; written in global components to FW[D][9][n].
+template <int DIM, int D, int LIM, int RS, class R>
+__device__ __forceinline__ void glm_face(const double* __restrict__ PW, double* __restrict__ FW,
+                                         const Geom& g, int i, int j, int k, int64_t c, R ch) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  // face frame (rho, v_n, v_t1, v_t2, B_t1, B_t2, p), then B_n and psi
+  constexpr int slot[9] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4, 5 + D, 8};
+  constexpr int NS = (LIM == 2) ? 6 : 4, O0 = (LIM == 2) ? 3 : 2;
+  const int64_t n = g.n;
+  int64_t cs[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int o = s - O0;
+    cs[s] = lin(g, D == 0 ? wrap_any(i + o, g.nx) : i, D == 1 ? wrap_any(j + o, g.ny) : j,
+                D == 2 ? wrap_any(k + o, g.nz) : k);
+  }
+  R wl[9], wr[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const double* w = PW + slot[q] * n;
+    if constexpr (LIM == 2) {
+      double v[6];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) v[s] = w[cs[s]];
+      wl[q] = (R)wenoz_upper(v[0], v[1], v[2], v[3], v[4]);
+      wr[q] = (R)wenoz_upper(v[5], v[4], v[3], v[2], v[1]);
+    } else {
+      R v[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[s] = (R)w[cs[s]];
+      wl[q] = fma_r(R(0.5), plm_slope<LIM, R>(v[1] - v[0], v[2] - v[1]), v[1]);
+      wr[q] = fma_r(R(-0.5), plm_slope<LIM, R>(v[2] - v[1], v[3] - v[2]), v[2]);
+    }
+  }
+  const R bns = R(0.5) * (wl[7] + wr[7]) - div_r(wr[8] - wl[8], R(2) * ch);
+  const R psis = R(0.5) * (wl[8] + wr[8]) - R(0.5) * ch * (wr[7] - wl[7]);
+  RiemannOut<R> o;
+  riemann<RS, R>((R)g.gamma, wl, wr, bns, o);
+  R* fw = stored<R>(FW) + (int64_t)D * kGlmFields * n + c;
+  fw[0 * n] = o.f[0];
+  fw[(1 + D) * n] = o.f[1];
+  fw[(1 + T1) * n] = o.f[2];
+  fw[(1 + T2) * n] = o.f[3];
+  fw[4 * n] = o.f[6];
+  fw[(5 + T1) * n] = o.f[4];
+  fw[(5 + T2) * n] = o.f[5];
+  fw[(5 + D) * n] = psis;
+  fw[8 * n] = ch * ch * bns;
+}
+
+// c_h = C Delta_min / dt, the largest speed the step's time step allows.
+template <int DIM, int LIM, int RS, class R>
+__global__ __launch_bounds__(kBlock) void k_glm_faces(const double* __restrict__ PW,
+                                                 double* __restrict__ FW, Geom g, double cfl,
+                                                 double dmin, double dt,
+                                                 const double* __restrict__ dtp) {
+  int i, j, k;
+  int64_t c;
+  if (!linear_cell(g, i, j, k, c)) return;
+  const double h = dtp ? *dtp : dt;
+  const R ch = (R)(cfl * dmin / h);
+  glm_face<DIM, 0, LIM, RS, R>(PW, FW, g, i, j, k, c, ch);
+  glm_face<DIM, 1, LIM, RS, R>(PW, FW, g, i, j, k, c, ch);
+  if (DIM == 3) glm_face<DIM, 2, LIM, RS, R>(PW, FW, g, i, j, k, c, ch);
+}
+
+// STAGE as in k_update (0: out = L(U); 1, 2: SSP-RK2; 1, 4, 5: SSP-RK3); in
+// the last stage of a step (2 or 5) psi is multiplied by the damping factor
+// exp(-alpha c_h dt / Delta_min).
+template <int DIM, int STAGE, class R>
+__global__ __launch_bounds__(kBlock) void k_glm_update(const double* __restrict__ U,
+                                                  const double* U0, double* out,
+                                                  const double* __restrict__ FW, Geom g,
+                                                  double dt, const double* __restrict__ dtp,
+                                                  double decay) {
+  int i, j, k;
+  int64_t c;
+  if (!linear_cell(g, i, j, k, c)) return;
+  const int64_t n = g.n;
+  const double h = (STAGE == 0) ? 0.0 : (dtp ? *dtp : dt);
+  const int64_t xp = lin(g, wrap(i + 1, g.nx), j, k);
+  const int64_t yp = lin(g, i, wrap(j + 1, g.ny), k);
+  const int64_t zp = (DIM == 3) ? lin(g, i, j, wrap(k + 1, g.nz)) : c;
+  const double idx = 1.0 / g.dx, idy = 1.0 / g.dy, idz = 1.0 / g.dz;
+  const R* fx = stored<R>(FW);
+  const R* fy = fx + (int64_t)kGlmFields * n;
+  const R* fz = fx + (int64_t)2 * kGlmFields * n;
+#pragma unroll
+  for (int q = 0; q < kGlmFields; ++q) {
+    double acc = ((double)fx[q * n + xp] - (double)fx[q * n + c]) * idx +
+                 ((double)fy[q * n + yp] - (double)fy[q * n + c]) * idy;
+    if (DIM == 3) acc += ((double)fz[q * n + zp] - (double)fz[q * n + c]) * idz;
+    const double Lq = -acc;
+    double v;
+    if (STAGE == 0) v = Lq;
+    else if (STAGE == 1) v = U[q * n + c] + h * Lq;
+    else if (STAGE == 4) v = (3.0 * U0[q * n + c] + (U[q * n + c] + h * Lq)) / 4.0;
+    else if (STAGE == 5) v = (U0[q * n + c] + 2.0 * (U[q * n + c] + h * Lq)) / 3.0;
+    else v = 0.5 * (U0[q * n + c] + (U[q * n + c] + h * Lq));
+    if ((STAGE == 2 || STAGE == 5) && q == 8) v = v * decay;
+    out[q * n + c] = v;
+  }
+}
+
+template <int DIM, int LIM, int RS, class R>
+hipError_t glm_stage_impl(const StageArgs& a) {
+  const unsigned nl = (unsigned)((a.g.n + kBlock - 1) / kBlock);
+  if (!a.PW) return hipErrorInvalidValue;
+  MHD_TIMED(a, K_PRIM,
+            hipLaunchKernelGGL((k_glm_prim<DIM>), dim3(nl), dim3(kBlock), 0, a.stream, a.U, a.PW,
+                               a.g, a.flag, a.cfl_partial));
+  if (a.cfl_partial)  // dt of the state U, before the faces read it
+    MHD_TIMED(a, K_CFL_FINAL,
+              hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, a.cfl_partial,
+                                 (int)nl, a.cfl, a.dt_out));
+  MHD_TIMED(a, K_FACES,
+            hipLaunchKernelGGL((k_glm_faces<DIM, LIM, RS, R>), dim3(nl), dim3(kBlock), 0, a.stream,
+                               a.PW, a.FW, a.g, a.cfl, a.glm_dmin, a.dt, a.dtp));
+#define MHD_GLM_UPD(ST)                                                                      \
+  MHD_TIMED(a, K_UPDATE,                                                                     \
+            hipLaunchKernelGGL((k_glm_update<DIM, ST, R>), dim3(nl), dim3(kBlock), 0, a.stream, \
+                               a.U, a.U0, a.out, a.FW, a.g, a.dt, a.dtp, a.glm_decay))
+  switch (a.stage) {
+    case 0: MHD_GLM_UPD(0); break;
+    case 1: MHD_GLM_UPD(1); break;
+    case 4: MHD_GLM_UPD(4); break;
+    case 5: MHD_GLM_UPD(5); break;
+    default: MHD_GLM_UPD(2); break;
+  }
+#undef MHD_GLM_UPD
+  return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t glm_stage_lim(const StageArgs& a) {
+  const bool mixed = a.precision == 1;
+  if (a.limiter == 2) {
+    if (mixed) return hipErrorInvalidValue;
+    return a.riemann == 0 ? glm_stage_impl<DIM, 2, 0, double>(a)
+                          : glm_stage_impl<DIM, 2, 1, double>(a);
+  }
+  if (a.limiter == 0) {
+    if (a.riemann == 0)
+      return mixed ? glm_stage_impl<DIM, 0, 0, float>(a) : glm_stage_impl<DIM, 0, 0, double>(a);
+    return mixed ? glm_stage_impl<DIM, 0, 1, float>(a) : glm_stage_impl<DIM, 0, 1, double>(a);
+  }
+  if (a.riemann == 0)
+    return mixed ? glm_stage_impl<DIM, 1, 0, float>(a) : glm_stage_impl<DIM, 1, 0, double>(a);
+  return mixed ? glm_stage_impl<DIM, 1, 1, float>(a) : glm_stage_impl<DIM, 1, 1, double>(a);
+}
+
 unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <class T>
@@ -947,7 +1183,7 @@ MarchGrid march_grid(const Geom& g) {
   return mg;
 }
 
-template <int DIM, int LIM, int RS, class R>
+template <int DIM, int LIM, int RS, class R, int EM>
 hipError_t stage_impl(const StageArgs& a) {
   // LIM 2 (WENO-Z, FP64): faces by k_faces_weno, edge values by van Leer PLM
   constexpr int ELIM = (LIM == 2) ? 1 : LIM;
@@ -965,12 +1201,12 @@ hipError_t stage_impl(const StageArgs& a) {
                 hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, a.cfl_partial,
                                    (int)nl, a.cfl, a.dt_out));
     MHD_TIMED(a, K_FACES,
-              hipLaunchKernelGGL((k_faces_weno<DIM, RS>), dim3(nl), dim3(kBlock), 0, a.stream,
+              hipLaunchKernelGGL((k_faces_weno<DIM, RS, EM>), dim3(nl), dim3(kBlock), 0, a.stream,
                                  a.PW, a.U, a.FW, a.g));
   } else if constexpr (DIM == 3) {
     const MarchGrid mg = march_grid(a.g);
     MHD_TIMED(a, K_FACES,
-              hipLaunchKernelGGL((k_faces_march<LIM, RS, R>), dim3(mg.nblocks), dim3(kBlock), 0,
+              hipLaunchKernelGGL((k_faces_march<LIM, RS, R, EM>), dim3(mg.nblocks), dim3(kBlock), 0,
                                  a.stream, a.U, a.FW, a.g, mg, a.flag, a.cfl_partial));
     if (a.cfl_partial)  // dt of the state U, before the update kernels read it
       MHD_TIMED(a, K_CFL_FINAL,
@@ -979,10 +1215,10 @@ hipError_t stage_impl(const StageArgs& a) {
   } else {
     const TileGrid tg = tile_grid<Tile<DIM>>(a.g);
     MHD_TIMED(a, K_FACES,
-              hipLaunchKernelGGL((k_faces_tiled<DIM, LIM, RS, R>), dim3(tg.ntiles),
+              hipLaunchKernelGGL((k_faces_tiled<DIM, LIM, RS, R, EM>), dim3(tg.ntiles),
                                  dim3(Tile<DIM>::NCORE), 0, a.stream, a.U, a.FW, a.g, tg, a.flag));
   }
-  if constexpr (DIM == 3) {
+  if constexpr (DIM == 3 && EM == 0) {
     MarchGrid eg;
     eg.ntx = (a.g.nx + EmfCol::TX - 1) / EmfCol::TX;
     eg.nty = (a.g.ny + EmfCol::TY - 1) / EmfCol::TY;
@@ -994,7 +1230,7 @@ hipError_t stage_impl(const StageArgs& a) {
                                  a.stream, a.U, a.FW, a.EW, a.g, eg));
   } else {
     MHD_TIMED(a, K_EMF,
-              hipLaunchKernelGGL((k_emf<DIM, ELIM, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+              hipLaunchKernelGGL((k_emf<DIM, ELIM, R, EM>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                  a.FW, a.EW, a.g, rg));
   }
   switch (a.stage) {
@@ -1029,31 +1265,51 @@ hipError_t stage_impl(const StageArgs& a) {
   return hipGetLastError();
 }
 
-template <int DIM>
+template <int DIM, int EM>
 hipError_t stage_lim(const StageArgs& a) {
   const bool mixed = a.precision == 1;
   if (a.limiter == 2) {  // WENO-Z: FP64 only
     if (mixed) return hipErrorInvalidValue;
-    return a.riemann == 0 ? stage_impl<DIM, 2, 0, double>(a) : stage_impl<DIM, 2, 1, double>(a);
+    return a.riemann == 0 ? stage_impl<DIM, 2, 0, double, EM>(a)
+                          : stage_impl<DIM, 2, 1, double, EM>(a);
   }
   if (a.limiter == 0) {
     if (a.riemann == 0)
-      return mixed ? stage_impl<DIM, 0, 0, float>(a) : stage_impl<DIM, 0, 0, double>(a);
-    return mixed ? stage_impl<DIM, 0, 1, float>(a) : stage_impl<DIM, 0, 1, double>(a);
+      return mixed ? stage_impl<DIM, 0, 0, float, EM>(a) : stage_impl<DIM, 0, 0, double, EM>(a);
+    return mixed ? stage_impl<DIM, 0, 1, float, EM>(a) : stage_impl<DIM, 0, 1, double, EM>(a);
   }
   if (a.riemann == 0)
-    return mixed ? stage_impl<DIM, 1, 0, float>(a) : stage_impl<DIM, 1, 0, double>(a);
-  return mixed ? stage_impl<DIM, 1, 1, float>(a) : stage_impl<DIM, 1, 1, double>(a);
+    return mixed ? stage_impl<DIM, 1, 0, float, EM>(a) : stage_impl<DIM, 1, 0, double, EM>(a);
+  return mixed ? stage_impl<DIM, 1, 1, float, EM>(a) : stage_impl<DIM, 1, 1, double, EM>(a);
 }
 
 }  // namespace
 
-size_t stage_cfl_blocks(const Geom& g, int limiter) {
-  return (limiter == 2) ? (size_t)((g.n + kBlock - 1) / kBlock) : march_grid(g).nblocks;
+size_t stage_cfl_blocks(const Geom& g, int limiter, bool glm) {
+  if (glm || limiter == 2) return (size_t)((g.n + kBlock - 1) / kBlock);
+  return march_grid(g).nblocks;
+}
+
+hipError_t launch_glm_cfl(const CflArgs& a, double* PW) {
+  const unsigned nl = (unsigned)((a.g.n + kBlock - 1) / kBlock);
+  if (a.dim == 3)
+    MHD_TIMED(a, K_CFL,
+              hipLaunchKernelGGL((k_glm_prim<3>), dim3(nl), dim3(kBlock), 0, a.stream, a.U, PW,
+                                 a.g, a.flag, a.partial));
+  else
+    MHD_TIMED(a, K_CFL,
+              hipLaunchKernelGGL((k_glm_prim<2>), dim3(nl), dim3(kBlock), 0, a.stream, a.U, PW,
+                                 a.g, a.flag, a.partial));
+  MHD_TIMED(a, K_CFL_FINAL,
+            hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, a.partial, (int)nl,
+                               a.cfl, a.dt_out));
+  return hipGetLastError();
 }
 
 hipError_t launch_stage(const StageArgs& a) {
-  return (a.dim == 3) ? stage_lim<3>(a) : stage_lim<2>(a);
+  if (a.glm) return (a.dim == 3) ? glm_stage_lim<3>(a) : glm_stage_lim<2>(a);
+  if (a.emf == 1) return (a.dim == 3) ? stage_lim<3, 1>(a) : stage_lim<2, 1>(a);
+  return (a.dim == 3) ? stage_lim<3, 0>(a) : stage_lim<2, 0>(a);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,6 +20,10 @@ struct Timer {
 // One RK stage (or the bare right-hand side).
 struct StageArgs {
   int dim, limiter, riemann, precision;
+  int emf;                // 0: upwind average with the HLL bounds; 1: UCT-HLLD
+  bool glm;               // GLM divergence cleaning: nine cell-centred fields, no CT
+  double glm_dmin;        // GLM: the smallest cell spacing (c_h = cfl dmin / dt)
+  double glm_decay;       // GLM: damping factor of psi per step, exp(-alpha cfl)
   int stage;              // 0: out = L(U); 1: out = U + dt L; 2: out = (U0 + U + dt L)/2;
                           // 3: face/edge records only; SSP-RK3 stages 2 and 3:
                           // 4: out = (3 U0 + (U + dt L))/4; 5: out = (U0 + 2 (U + dt L))/3
@@ -65,8 +69,11 @@ struct CflArgs {
   } while (0)
 
 hipError_t launch_stage(const StageArgs& a);
-// number of CFL partials the 3D face kernel writes (one per workgroup)
-size_t stage_cfl_blocks(const Geom& g, int limiter);
+// number of CFL partials the 3D face kernel (WENO-Z, GLM: primitive kernel)
+// writes (one per workgroup)
+size_t stage_cfl_blocks(const Geom& g, int limiter, bool glm);
+// GLM: the CFL time step of U through its primitive kernel (writes PW too)
+hipError_t launch_glm_cfl(const CflArgs& a, double* PW);
 hipError_t launch_cfl(const CflArgs& a);
 // Partials of the allocation-free CFL time step (a file-scope device array of
 // that many doubles plus the flag; nblocks must not exceed it).

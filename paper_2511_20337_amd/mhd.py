@@ -27,6 +27,8 @@ LIMITERS = {"minmod": 0, "vanleer": 1, "wenoz": 2}
 SOLVERS = {"hlld": 0, "hll": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 INTEGRATORS = {"rk2": 0, "rk3": 1}
+EMFS = {"uct_hll": 0, "uct_hlld": 1}
+DIVB = {"ct": 0, "glm": 1}
 
 # Every symbol include/mhd.h declares.
 SYMBOLS = ("mhd_init", "mhd_destroy", "mhd_workspace_bytes", "mhd_dt", "mhd_dt_device",
@@ -46,6 +48,7 @@ class mhd_config(ctypes.Structure):  # noqa: N801 — C name
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
         ("limiter", ctypes.c_int32), ("riemann", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("integrator", ctypes.c_int32),
+        ("emf", ctypes.c_int32), ("divb", ctypes.c_int32),
     ]
 
 
@@ -113,7 +116,8 @@ def config_from(setup: dict) -> mhd_config:
                       b[0], b[1], b[2], b[3], b[4], b[5], float(setup["gamma"]),
                       float(setup["cfl"]), LIMITERS[setup["limiter"]], SOLVERS[setup["riemann"]],
                       PRECISIONS[setup.get("precision", "fp64")],
-                      INTEGRATORS[setup.get("integrator", "rk2")])
+                      INTEGRATORS[setup.get("integrator", "rk2")],
+                      EMFS[setup.get("emf", "uct_hll")], DIVB[setup.get("divb", "ct")])
 
 
 # ---------------------------------------------------------------- C names --
@@ -246,7 +250,8 @@ class Context:
         self.setup = dict(setup)
         self.cfg = config_from(setup)
         self.device = torch.device(device)
-        self.shape = (8, int(setup["nz"]), int(setup["ny"]), int(setup["nx"]))
+        nf = 9 if setup.get("divb", "ct") == "glm" else 8  # GLM adds psi
+        self.shape = (nf, int(setup["nz"]), int(setup["ny"]), int(setup["nx"]))
         self.ctx = mhd_init(self.cfg)
         nbytes = mhd_workspace_bytes(self.ctx, with_adjoint)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

@@ -44,8 +44,10 @@ def _cf(W, bx, g):
     return np.sqrt((a + np.sqrt(np.maximum(0.0, a * a - 4 * gp * bx * bx))) / (2 * rho))
 
 
-def rhs(Uc, bx, dx, g, lim):
-    """Uc: (7, n) = (rho, m_x, m_y, m_z, B_y, B_z, E); periodic."""
+def rhs(Uc, bx, dx, g, lim, flux=None):
+    """Uc: (7, n) = (rho, m_x, m_y, m_z, B_y, B_z, E); periodic. flux: an
+    optional face flux flux(WL, WR, bx, g) -> (7, n) in place of the HLL one
+    (used to check the scheme against another single-face solver)."""
     rho = Uc[0]
     u, v, w = Uc[1] / rho, Uc[2] / rho, Uc[3] / rho
     by, bz = Uc[4], Uc[5]
@@ -58,6 +60,9 @@ def rhs(Uc, bx, dx, g, lim):
     # face f is the lower face of cell f: left state from cell f-1, right from f
     WL = np.roll(W + 0.5 * S, 1, axis=1)
     WR = W - 0.5 * S
+    if flux is not None:
+        Fh = flux(WL, WR, bx, g)
+        return -(np.roll(Fh, -1, axis=1) - Fh) / dx
     UL, FL = _flux_and_cons(WL, bx, g)
     UR, FR = _flux_and_cons(WR, bx, g)
     cmax = np.maximum(_cf(WL, bx, g), _cf(WR, bx, g))
@@ -69,6 +74,6 @@ def rhs(Uc, bx, dx, g, lim):
     return -(np.roll(Fh, -1, axis=1) - Fh) / dx
 
 
-def step(Uc, bx, dx, dt, g, lim):
-    U1 = Uc + dt * rhs(Uc, bx, dx, g, lim)
-    return 0.5 * (Uc + (U1 + dt * rhs(U1, bx, dx, g, lim)))
+def step(Uc, bx, dx, dt, g, lim, flux=None):
+    U1 = Uc + dt * rhs(Uc, bx, dx, g, lim, flux)
+    return 0.5 * (Uc + (U1 + dt * rhs(U1, bx, dx, g, lim, flux)))

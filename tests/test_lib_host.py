@@ -33,7 +33,8 @@ def test_init_validates_config():
     assert mhd.mhd_workspace_bytes(ctx, True) >= fwd
     mhd.mhd_destroy(ctx)
     bad = [("dim", 4), ("nx", 3), ("nz", 2), ("gamma", 1.0), ("cfl", 0.0), ("cfl", float("nan")),
-           ("xmax", 0.0), ("limiter", 3), ("riemann", -1), ("precision", 3), ("integrator", 2)]
+           ("xmax", 0.0), ("limiter", 3), ("riemann", -1), ("precision", 3), ("integrator", 2),
+           ("emf", 2), ("emf", -1), ("divb", 2)]
     for field, value in bad:
         cfg = mhd.config_from(s)
         setattr(cfg, field, value)
@@ -46,6 +47,14 @@ def test_init_validates_config():
         mhd.mhd_init(cfg)
     assert e.value.status == mhd.MHD_ERR_INVALID
     mhd.mhd_destroy(mhd.mhd_init(mhd.config_from(dict(s, limiter="wenoz"))))
+    # the UCT-HLLD average; GLM cleaning, which has no edge EMF to select
+    mhd.mhd_destroy(mhd.mhd_init(mhd.config_from(dict(s, emf="uct_hlld"))))
+    ctx = mhd.mhd_init(mhd.config_from(dict(s, divb="glm")))
+    assert mhd.mhd_workspace_bytes(ctx) >= 9 * 8 * n  # nine-field stage-1 state
+    mhd.mhd_destroy(ctx)
+    with pytest.raises(mhd.MHDError) as e:
+        mhd.mhd_init(mhd.config_from(dict(s, divb="glm", emf="uct_hlld")))
+    assert e.value.status == mhd.MHD_ERR_INVALID
     s2, _ = W.orszag_tang_2d(8)
     cfg = mhd.config_from(s2)
     cfg.nz = 4  # 2D needs nz == 1

@@ -241,15 +241,32 @@ def test_axis_permutation_symmetry_3d():
     np.testing.assert_allclose(A, B, rtol=0, atol=1e-13 * np.abs(B).max())
 
 
-@pytest.mark.parametrize("dim,axis", [(2, 0), (2, 1), (3, 0), (3, 2)])
-def test_plane_parallel_equals_1d_hll(dim, axis):
-    """With HLL and no transverse variation the 2D/3D scheme, including the
-    CT EMF, reduces to an independently written 1D HLL scheme."""
+def _hlld_face_flux(WL, WR, bx, g):
+    """Face fluxes of the oracle's single-face HLLD solver (pinned on its own
+    in test_oracle_units) for the 1D reference scheme."""
+    out = np.zeros(WL.shape)
+    for f in range(WL.shape[1]):
+        out[:, f] = O.riemann(WL[:, f], WR[:, f], bx, gamma=g, solver="hlld")[:7]
+    return out
+
+
+@pytest.mark.parametrize("dim,axis,solver,emf",
+                         [(2, 0, "hll", "uct_hll"), (2, 1, "hll", "uct_hll"),
+                          (3, 0, "hll", "uct_hll"), (3, 2, "hll", "uct_hll"),
+                          (2, 0, "hlld", "uct_hlld"), (2, 1, "hlld", "uct_hlld"),
+                          (3, 1, "hlld", "uct_hlld"), (3, 2, "hlld", "uct_hlld"),
+                          (3, 0, "hll", "uct_hlld")])
+def test_plane_parallel_equals_1d_hll(dim, axis, solver, emf):
+    """With no transverse variation the 2D/3D scheme, including the CT EMF,
+    reduces to a 1D scheme with the same face solver: with HLL and either
+    average, the independently written 1D HLL scheme; with HLLD and the
+    UCT-HLLD average, the 1D scheme with the HLLD face flux (the edge EMFs
+    equal minus the HLLD fluxes of the transverse field components)."""
     n = 64
     nn = [4, 4, 1 if dim == 2 else 4]
     nn[axis] = n
     s = W.make_setup("plane", dim, nn[0], nn[1], nn[2], (0, 1, 0, 1, 0, 1), 5 / 3, 0.4,
-                     "vanleer", "hll")
+                     "vanleer", solver, emf=emf)
     xs = (np.arange(n) + 0.5) / n
     g = 5 / 3
     rho = 1.0 + 0.3 * np.sin(2 * np.pi * xs)
@@ -274,9 +291,10 @@ def test_plane_parallel_equals_1d_hll(dim, axis):
     E = p / (g - 1) + 0.5 * rho * (un ** 2 + v1 ** 2 + v2 ** 2) + 0.5 * (bn ** 2 + b1 ** 2 + b2 ** 2)
     U1d = np.stack([rho, rho * un, rho * v1, rho * v2, b1, b2, E])
     dt = 0.4 / n / 3.0
+    flux = _hlld_face_flux if solver == "hlld" else None
     for _ in range(10):
         U = O.step(c, U, dt)
-        U1d = ref_mhd1d.step(U1d, bn, 1.0 / n, dt, g, "vanleer")
+        U1d = ref_mhd1d.step(U1d, bn, 1.0 / n, dt, g, "vanleer", flux)
     line = [slice(0, 1)] * 3
     line[2 - axis] = slice(None)
 
@@ -286,6 +304,45 @@ def test_plane_parallel_equals_1d_hll(dim, axis):
     mapping = [(0, 0), (1 + axis, 1), (1 + t1, 2), (1 + t2, 3), (5 + t1, 4), (5 + t2, 5), (4, 6)]
     for q3, q1 in mapping:
         np.testing.assert_allclose(get(q3), U1d[q1], rtol=1e-12, atol=1e-13)
+
+
+def test_plane_parallel_hlld_with_uct_hll_is_not_1d_hlld():
+    """The mismatch the UCT-HLLD average removes: with HLLD fluxes but the
+    HLL-coefficient upwind EMF, the transverse field of a plane-parallel run
+    follows the HLL flux, not the HLLD one, so the run departs from the 1D
+    HLLD scheme (by far more than round-off) while the cell fields' fluxes
+    are HLLD."""
+    n = 64
+    s = W.make_setup("plane", 2, n, 4, 1, (0, 1, 0, 1, 0, 1), 5 / 3, 0.4, "vanleer", "hlld")
+    xs = (np.arange(n) + 0.5) / n
+    g = 5 / 3
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * xs)
+    un = 0.2 * np.cos(2 * np.pi * xs)
+    v1, v2 = 0.3 * np.sin(4 * np.pi * xs), -0.1 + 0.2 * np.cos(2 * np.pi * xs)
+    b1, b2 = 0.5 * np.cos(2 * np.pi * xs), 0.4 * np.sin(2 * np.pi * xs + 1)
+    p = 0.8 + 0.1 * np.where(xs > 0.5, 1.0, 0.0)
+    bn = 0.7
+
+    def f(a):
+        return np.broadcast_to(a[None, None, :], (1, 4, n))
+    U0 = W.assemble(s, f(rho), f(un), f(v1), f(v2), f(p), f(np.full(n, bn)), f(b1), f(b2))
+    E = p / (g - 1) + 0.5 * rho * (un ** 2 + v1 ** 2 + v2 ** 2) + 0.5 * (bn ** 2 + b1 ** 2 + b2 ** 2)
+    U1d = np.stack([rho, rho * un, rho * v1, rho * v2, b1, b2, E])
+    dt = 0.4 / n / 3.0
+    res = {}
+    for emf in ("uct_hll", "uct_hlld"):
+        c = O.cfg_from(dict(s, emf=emf))
+        U = U0
+        for _ in range(10):
+            U = O.step(c, U, dt)
+        res[emf] = U[6, 0, 0, :]  # b_y (t1 of the x-normal)
+    R1 = U1d
+    for _ in range(10):
+        R1 = ref_mhd1d.step(R1, bn, 1.0 / n, dt, g, "vanleer", _hlld_face_flux)
+    err_hlld = np.abs(res["uct_hlld"] - R1[4]).max()
+    err_hll = np.abs(res["uct_hll"] - R1[4]).max()
+    assert err_hlld <= 1e-13
+    assert err_hll >= 1e-6, err_hll
 
 
 # ------------------------------------------------------ tangent vs FD ------

@@ -505,3 +505,76 @@ def test_count_ops_matches_hand_count(dim, solver):
     kinds = ("add", "mul", "div", "sqrt")
     for ph, w in want.items():
         assert tuple(got[ph][k] for k in kinds) == tuple(cells * x for x in w), (ph, got[ph], w)
+
+
+# ------------------------------------------------------- UCT-HLLD coefficients ---
+def _face_states(rng, m):
+    """Random face states over every region of both solvers: normal velocities
+    from supersonic leftward to supersonic rightward, normal fields including
+    zero, transverse fields including zero (degenerate HLLD star states)."""
+    out = []
+    for t in range(m):
+        wl = np.array([rng.uniform(0.3, 2.0), rng.uniform(-3.0, 3.0), rng.normal(), rng.normal(),
+                       rng.normal(), rng.normal(), rng.uniform(0.1, 2.0)])
+        wr = np.array([rng.uniform(0.3, 2.0), rng.uniform(-3.0, 3.0), rng.normal(), rng.normal(),
+                       rng.normal(), rng.normal(), rng.uniform(0.1, 2.0)])
+        shift = rng.choice([0.0, -4.0, 4.0, -1.2, 1.2])
+        wl[1] += shift
+        wr[1] += shift
+        bn = rng.choice([0.0, rng.normal(), 2.0 * rng.normal(), 1e-3 * rng.normal()])
+        if t % 7 == 0:
+            wl[4:6] = 0.0
+            wr[:] = wl
+            bn = 1.5  # Alfven speed above the sound speed: degenerate star states
+        out.append((wl, wr, float(bn)))
+    return out
+
+
+@pytest.mark.parametrize("solver", ["hlld", "hll"])
+def test_uct_hlld_coefficients_reproduce_transverse_field_flux(solver):
+    """[reading R19] The flux of each transverse field component equals
+    chiL B_t^L + chiR B_t^R - B_n (om v_t^L + (1 - om) v_t^R), with
+    chiL = om u_L + d^L and chiR = (1 - om) u_R - d^R, for both components, in
+    every region; the face velocities are the om-weighted ones."""
+    rng = np.random.default_rng(31)
+    seen = set()
+    for wl, wr, bn in _face_states(rng, 3000):
+        o = O.riemann(wl, wr, bn, solver=solver)
+        om, dl, dr = o[11], o[12], o[13]
+        chiL = om * wl[1] + dl
+        chiR = (1.0 - om) * wr[1] - dr
+        for comp in (0, 1):
+            B_L, B_R, v_L, v_R = wl[4 + comp], wr[4 + comp], wl[2 + comp], wr[2 + comp]
+            F = chiL * B_L + chiR * B_R - bn * (om * v_L + (1.0 - om) * v_R)
+            scale = 1.0 + np.abs(o[4 + comp]) + np.abs(chiL * B_L) + np.abs(chiR * B_R) + \
+                np.abs(bn) * (np.abs(v_L) + np.abs(v_R))
+            assert abs(F - o[4 + comp]) <= 1e-13 * scale, (wl, wr, bn, comp, F, o[4 + comp])
+            assert o[14 + comp] == pytest.approx(om * v_L + (1.0 - om) * v_R, rel=1e-14,
+                                                 abs=1e-14)
+        seen.add("0" if om == 0.0 else ("1" if om == 1.0 else "mid"))
+        if solver == "hll":
+            ap, am = o[7], o[8]
+            assert om == pytest.approx(ap / (ap + am), rel=1e-15)
+            assert dl == pytest.approx(ap * am / (ap + am), rel=1e-14, abs=1e-300)
+            assert dr == dl
+    assert seen == {"0", "1", "mid"}
+
+
+def test_uct_hlld_weight_is_the_transverse_velocity_coefficient():
+    """[reading R19] The HLLD wave structure does not depend on the
+    transverse velocities, so the transverse field flux is exactly linear in
+    them: raising v_t^L (or v_t^R) by delta changes F[B_t] by -B_n om delta
+    (by -B_n (1 - om) delta)."""
+    rng = np.random.default_rng(32)
+    for wl, wr, bn in _face_states(rng, 1500):
+        o = O.riemann(wl, wr, bn, solver="hlld")
+        om = o[11]
+        for comp in (0, 1):
+            for side, w0 in ((0, wl), (1, wr)):
+                w = w0.copy()
+                w[2 + comp] += 0.37
+                o2 = O.riemann(w if side == 0 else wl, wr if side == 0 else w, bn, solver="hlld")
+                weight = om if side == 0 else 1.0 - om
+                dF = o2[4 + comp] - o[4 + comp]
+                assert dF == pytest.approx(-bn * weight * 0.37,
+                                           abs=1e-13 * (1 + abs(o[4 + comp]) + abs(o2[4 + comp])))
