@@ -226,6 +226,13 @@ def only_part(part, n, steps, warmup):
                "ms_per_step": el / steps * 1e3,
                "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]},
                "roofline": weno_roofline(kt, n ** 3)}
+    elif part == "glm":
+        sg, Ug = W.glm_from_ct(*W.turbulence_3d(n))
+        el, kt, _, phys = time_gpu(sg, Ug, steps, warmup)
+        out = {"part": part, "value": n ** 3 * steps / el / 1e6, "unit": "Mcell-updates/s",
+               "workload": "turbulence_3d_%d glm" % n, "physical": phys,
+               "ms_per_step": el / steps * 1e3,
+               "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]}}
     elif part == "adjoint":
         adj, fwd = time_adjoint(512, 64, 8)
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
@@ -253,7 +260,8 @@ def main(argv=None):
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters) and exit")
-    ap.add_argument("--only", choices=("mixed", "ot3d_wenoz", "adjoint", "adjoint_3d", "adjoint_3d_rk3"), default=None,
+    ap.add_argument("--only", choices=("mixed", "ot3d_wenoz", "glm", "adjoint", "adjoint_3d",
+                                       "adjoint_3d_rk3"), default=None,
                     help="run only this extra measurement and print it (for profiling)")
     args = ap.parse_args(argv)
     if args.copy_probe:
@@ -365,6 +373,16 @@ def main(argv=None):
             "ms_per_step": el_ow / steps_o * 1e3, "physical": phys_ow,
             "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_ow.items() if v[1]},
             "roofline": weno_roofline(kt_ow, 352 ** 3)}
+        log("GLM divergence cleaning: the same turbulence %d^3 on nine cell-centred fields" % args.n)
+        sg, Ug = W.glm_from_ct(*W.turbulence_3d(args.n))
+        steps_g = max(1, args.steps // 5)
+        el_g, kt_g, _, phys_g = time_gpu(sg, Ug, steps_g, 1)
+        del Ug
+        out["glm"] = {"value": ncell * steps_g / el_g / 1e6, "unit": "Mcell-updates/s",
+                      "steps": steps_g, "ms_per_step": el_g / steps_g * 1e3, "physical": phys_g,
+                      "config": {"workload": "turbulence_3d_%d" % args.n, "divb": "glm",
+                                 "limiter": "vanleer", "riemann": "hlld", "integrator": "ssp_rk2"},
+                      "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_g.items() if v[1]}}
         log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, checkpoints every 8")
         adj, fwd = time_adjoint(512, 64, 8)
         out["adjoint"] = {"value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,

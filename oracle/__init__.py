@@ -77,6 +77,8 @@ def _load():
             ("oracle_step_jvp", [cp, dp, dp, ctypes.c_double, ctypes.c_double], ctypes.c_int),
             ("oracle_divb", [cp, dp, dp], ctypes.c_int),
             ("oracle_glm_dt", [cp, dp, dp], ctypes.c_int),
+            ("oracle_count_degenerate", [cp, dp, ctypes.POINTER(ctypes.c_longlong)],
+             ctypes.c_int),
             ("oracle_glm_run", [cp, dp, ctypes.c_int, dp], ctypes.c_int),
             ("oracle_glm_run_dts", [cp, dp, ctypes.c_int, dp], ctypes.c_int),
             ("oracle_glm_rhs", [cp, dp, dp, ctypes.c_double], ctypes.c_int),
@@ -323,3 +325,12 @@ def divb_centred(c: OCfg, U) -> np.ndarray:
     if c.dim == 3:
         d = d + (np.roll(U[7], -1, 0) - np.roll(U[7], 1, 0)) / (2 * dz)
     return d
+
+
+def count_degenerate(c: OCfg, U) -> dict:
+    """HLLD star sides evaluated and found degenerate in one right-hand side
+    of U, in FP64 and in the mixed (FP32) variant."""
+    U = _state(c, U)
+    out = (ctypes.c_longlong * 4)()
+    _check(_load().oracle_count_degenerate(ctypes.byref(c), _ptr(U), out))
+    return {"fp64": (int(out[0]), int(out[1])), "fp32": (int(out[2]), int(out[3]))}

@@ -40,6 +40,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 #include <algorithm>
 #ifdef _OPENMP
@@ -284,6 +285,11 @@ template <class R> R fast_speed(R g, R rho, R p, R bn, R bt1, R bt2) {
   return Sqrt((a + Sqrt(disc)) / (R(2) * rho));
 }
 
+// Diagnostic counters of the HLLD degeneracy test (star sides evaluated,
+// sides found degenerate), per working precision: [0] FP64, [1] FP32.
+long long g_deg_sides[2], g_deg_hits[2];
+template <class R> constexpr int prec_index() { return std::is_same<R, float>::value ? 1 : 0; }
+
 // Relative tolerance of the HLLD degeneracy test, per working precision.
 template <class R> struct DegTol { static constexpr double value = 1e-12; };
 template <> struct DegTol<float> { static constexpr double value = 1e-12 * 536870912.0; };
@@ -375,7 +381,12 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o,
     // [reading] degenerate case (S_alpha ~ S*_alpha): tangential fields
     // unchanged when |D| is within a relative tolerance of 1e-12 in FP64
     // units, scaled to the working precision (x 2^29 in FP32)
-    if (Abs(D) <= R(DegTol<R>::value) * (Abs(big) + bn * bn)) {
+    const bool degenerate = Abs(D) <= R(DegTol<R>::value) * (Abs(big) + bn * bn);
+#pragma omp atomic
+    g_deg_sides[prec_index<R>()] += 1;
+    if (degenerate) {
+#pragma omp atomic
+      g_deg_hits[prec_index<R>()] += 1;
       vs[s] = w[2]; ws[s] = w[3]; b1s[s] = w[4]; b2s[s] = w[5];
       zeta[s] = R(1);
       eta[s] = R(0);
@@ -1040,6 +1051,24 @@ int oracle_run_dts(const OCfg* cfg, double* U, int nsteps, const double* dts) {
     });
   }
   return bad ? -4 : 0;
+}
+
+// How often the HLLD star state is taken as degenerate in one right-hand
+// side of U, in FP64 and in the mixed (FP32) variant: out = {FP64 sides,
+// FP64 degenerate sides, FP32 sides, FP32 degenerate sides}.
+int oracle_count_degenerate(const OCfg* cfg, const double* U, long long* out) {
+  if (!cfg_ok(cfg) || !U || !out) return -1;
+  const Grid G(*cfg);
+  std::vector<double> L((size_t)NF * G.ncell);
+  for (int p = 0; p < 2; ++p) {
+    OCfg c = *cfg;
+    c.precision = p;
+    g_deg_sides[p] = g_deg_hits[p] = 0;
+    rhs_dispatch<double, double>(c, U, L.data());
+    out[2 * p] = g_deg_sides[p];
+    out[2 * p + 1] = g_deg_hits[p];
+  }
+  return 0;
 }
 
 // GLM divergence cleaning: nine cell-centred fields (rho, m, E, B, psi).

@@ -231,7 +231,35 @@ struct EmfCol {
   static constexpr int NT = TX * TY;  // workgroup size
 };
 
-template <int LIM, class R>
+// The coefficients of one face the edge average takes: alpha+ and alpha-
+// (EM 0), or the UCT-HLLD weight and diffusion coefficients (EM 1).
+template <int EM, class R>
+struct FaceCoef {
+  R c[EM == 1 ? 3 : 2];
+};
+template <int EM, class R>
+__device__ __forceinline__ FaceCoef<EM, R> face_coef(const R* f, int64_t n, int64_t c) {
+  FaceCoef<EM, R> o;
+  o.c[0] = f[S_AP * n + c];
+  o.c[1] = f[S_AM * n + c];
+  if constexpr (EM == 1) o.c[2] = f[S_DR * n + c];
+  return o;
+}
+// Edge EMF from the coefficients of the a-faces (below the edge along B,
+// then the cell's own) and b-faces, and the reconstructed values.
+template <int LIM, int EM, class R>
+__device__ __forceinline__ R emf_from(const FaceCoef<EM, R>& am, const FaceCoef<EM, R>& ac,
+                                      const FaceCoef<EM, R>& bm, const FaceCoef<EM, R>& bc,
+                                      const R* vbA, const R* bB, const R* vaB, const R* bA) {
+  if constexpr (EM == 1)
+    return emf_core_hlld<LIM, R>(am.c[0], ac.c[0], am.c[1], ac.c[1], am.c[2], ac.c[2], bm.c[0],
+                                 bc.c[0], bm.c[1], bc.c[1], bm.c[2], bc.c[2], vbA, bB, vaB, bA);
+  else
+    return emf_core<LIM, R>(am.c[0], ac.c[0], am.c[1], ac.c[1], bm.c[0], bc.c[0], bm.c[1],
+                            bc.c[1], vbA, bB, vaB, bA);
+}
+
+template <int LIM, class R, int EM>
 __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restrict__ U,
                                                       const double* __restrict__ FW,
                                                       double* __restrict__ EW, Geom g,
@@ -256,8 +284,9 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
   const double* by = U + F_BY * n;
   const double* bz = U + F_BZ * n;
   // planes k-2 .. k+1 of this column: v_z on y-faces and b_y (E_x), v_z on
-  // x-faces and b_x (E_y); alpha+- of y- and x-faces on planes k-1, k
-  R yv[4], yb[4], xv[4], xb[4], yap[2], yam[2], xap[2], xam[2];
+  // x-faces and b_x (E_y); the coefficients of y- and x-faces on planes k-1, k
+  R yv[4], yb[4], xv[4], xb[4];
+  FaceCoef<EM, R> yc[2], xc[2];
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int64_t cs = lin(g, i, j, wrap_any(k0 - 2 + s, g.nz));
@@ -268,10 +297,8 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
   }
   {
     const int64_t cm = lin(g, i, j, wrap_any(k0 - 1, g.nz));
-    yap[0] = fy[S_AP * n + cm];
-    yam[0] = fy[S_AM * n + cm];
-    xap[0] = fx[S_AP * n + cm];
-    xam[0] = fx[S_AM * n + cm];
+    yc[0] = face_coef<EM, R>(fy, n, cm);
+    xc[0] = face_coef<EM, R>(fx, n, cm);
   }
   const int im2 = wrap(i - 2, g.nx), im1 = wrap(i - 1, g.nx), ip1 = wrap(i + 1, g.nx);
   const int jm2 = wrap(j - 2, g.ny), jm1 = wrap(j - 1, g.ny), jp1 = wrap(j + 1, g.ny);
@@ -284,16 +311,16 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
     // FP64), then the conversions to R: the loads stay in flight together
     const R* vz2 = fz + S_V2 * n;
     const R* vz1 = fz + S_V1 * n;
-    R r[15];
+    R r[14];
     double d[9];
     r[0] = fy[S_V1 * n + cp]; r[1] = fx[S_V2 * n + cp];
-    r[2] = fy[S_AP * n + c]; r[3] = fy[S_AM * n + c]; r[4] = fx[S_AP * n + c];
-    r[5] = fx[S_AM * n + c];
+    yc[1] = face_coef<EM, R>(fy, n, c);
+    xc[1] = face_coef<EM, R>(fx, n, c);
     r[6] = vz2[cjm2]; r[7] = vz2[cjm1]; r[8] = vz2[c]; r[9] = vz2[cjp1];
     r[10] = vz1[cim2]; r[11] = vz1[cim1]; r[12] = vz1[c]; r[13] = vz1[cip1];
-    r[14] = fz[S_AP * n + cjm1];
-    const R zapc = fz[S_AP * n + c], zamj = fz[S_AM * n + cjm1], zamc = fz[S_AM * n + c];
-    const R zapi = fz[S_AP * n + cim1], zami = fz[S_AM * n + cim1];
+    const FaceCoef<EM, R> zjm = face_coef<EM, R>(fz, n, cjm1);
+    const FaceCoef<EM, R> zc0 = face_coef<EM, R>(fz, n, c);
+    const FaceCoef<EM, R> zim = face_coef<EM, R>(fz, n, cim1);
     d[0] = by[cp]; d[1] = bx[cp];
     d[2] = bz[cjm2]; d[3] = bz[cjm1]; d[4] = bz[c]; d[5] = bz[cjp1];
     d[6] = bz[cim2]; d[7] = bz[cim1]; d[8] = bz[cip1];
@@ -301,25 +328,19 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
     yb[3] = (R)d[0];
     xv[3] = r[1];
     xb[3] = (R)d[1];
-    yap[1] = r[2];
-    yam[1] = r[3];
-    xap[1] = r[4];
-    xam[1] = r[5];
     // E_x: (A, B) = (y, z); a-faces are y-faces, b-faces z-faces
     {
       const R wv[4] = {r[6], r[7], r[8], r[9]};
       const R wb[4] = {(R)d[2], (R)d[3], (R)d[4], (R)d[5]};
-      ew[c] = emf_core<LIM, R>(yap[0], yap[1], yam[0], yam[1], r[14], zapc, zamj, zamc, wv, wb,
-                               yv, yb);
+      ew[c] = emf_from<LIM, EM, R>(yc[0], yc[1], zjm, zc0, wv, wb, yv, yb);
     }
     // E_y: (A, B) = (z, x); a-faces are z-faces, b-faces x-faces
     {
       const R sv[4] = {r[10], r[11], r[12], r[13]};
       const R sb[4] = {(R)d[6], (R)d[7], (R)d[4], (R)d[8]};
-      ew[n + c] = emf_core<LIM, R>(zapi, zapc, zami, zamc, xap[0], xap[1], xam[0], xam[1], xv, xb,
-                                   sv, sb);
+      ew[n + c] = emf_from<LIM, EM, R>(zim, zc0, xc[0], xc[1], xv, xb, sv, sb);
     }
-    ew[2 * n + c] = emf_comp<2, LIM, R>(U, FW, g, i, j, k, c);
+    ew[2 * n + c] = emf_comp<2, LIM, R, EM>(U, FW, g, i, j, k, c);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       yv[s] = yv[s + 1];
@@ -327,10 +348,8 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
       xv[s] = xv[s + 1];
       xb[s] = xb[s + 1];
     }
-    yap[0] = yap[1];
-    yam[0] = yam[1];
-    xap[0] = xap[1];
-    xam[0] = xam[1];
+    yc[0] = yc[1];
+    xc[0] = xc[1];
   }
 }
 
@@ -1218,7 +1237,7 @@ hipError_t stage_impl(const StageArgs& a) {
               hipLaunchKernelGGL((k_faces_tiled<DIM, LIM, RS, R, EM>), dim3(tg.ntiles),
                                  dim3(Tile<DIM>::NCORE), 0, a.stream, a.U, a.FW, a.g, tg, a.flag));
   }
-  if constexpr (DIM == 3 && EM == 0) {
+  if constexpr (DIM == 3) {
     MarchGrid eg;
     eg.ntx = (a.g.nx + EmfCol::TX - 1) / EmfCol::TX;
     eg.nty = (a.g.ny + EmfCol::TY - 1) / EmfCol::TY;
@@ -1226,7 +1245,7 @@ hipError_t stage_impl(const StageArgs& a) {
     eg.nzc = (a.g.nz + eg.lz - 1) / eg.lz;
     eg.nblocks = (unsigned)eg.ntx * (unsigned)eg.nty * (unsigned)eg.nzc;
     MHD_TIMED(a, K_EMF,
-              hipLaunchKernelGGL((k_emf_march<ELIM, R>), dim3(eg.nblocks), dim3(EmfCol::NT), 0,
+              hipLaunchKernelGGL((k_emf_march<ELIM, R, EM>), dim3(eg.nblocks), dim3(EmfCol::NT), 0,
                                  a.stream, a.U, a.FW, a.EW, a.g, eg));
   } else {
     MHD_TIMED(a, K_EMF,

@@ -578,3 +578,18 @@ def test_uct_hlld_weight_is_the_transverse_velocity_coefficient():
                 dF = o2[4 + comp] - o[4 + comp]
                 assert dF == pytest.approx(-bn * weight * 0.37,
                                            abs=1e-13 * (1 + abs(o[4 + comp]) + abs(o2[4 + comp])))
+
+
+def test_degenerate_counter_on_an_aligned_uniform_state():
+    """The diagnostic count of degenerate HLLD star sides: in a uniform state
+    with the field along x and the Alfven speed above the sound speed every
+    x-face has identical states with D = 0 (both sides degenerate, in either
+    precision), while y- and z-faces (B_n = 0, D = rho (S-u)(S-S_M) != 0)
+    have none: 6n sides evaluated, 2n degenerate."""
+    s, U = W.aligned_field_bump(3, 8, 6, 5)
+    for q in range(8):
+        U[q] = U[q].flat[0]  # the plasma outside the bump, everywhere
+    n = 8 * 6 * 5
+    r = O.count_degenerate(O.cfg_from(s), U)
+    assert r["fp64"] == (6 * n, 2 * n)
+    assert r["fp32"] == (6 * n, 2 * n)
