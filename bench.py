@@ -56,6 +56,10 @@ FP32_PEAK = 157.3e12
 # HBM bytes per cell of one face-kernel launch, rocprofv3 FETCH_SIZE x 2.0 and
 # WRITE_SIZE x 1.0 (the copy-kernel calibration), for the kernel as it stands.
 FACE_TRAFFIC = {"fp64": 202.4 + 216.0, "mixed": 203.0 + 108.0}
+# HBM bytes per cell of one whole step, the same counters summed over its
+# launches (two of faces and EMF, the updates of both stages): what the
+# three-kernel stage moves beside the 320 algorithmic bytes.
+STEP_TRAFFIC = {"fp64": 2029.0, "mixed": 1356.0}
 # WENO-Z face kernel on the 3D Orszag-Tang problem (FP64, HLLD): algorithmic
 # flops per cell of the oracle's face phase on that workload at 256^3 (count_flops.py;
 # its textbook WENO-Z with seven divisions per value, each one flop), and the
@@ -307,6 +311,7 @@ def main(argv=None):
                    "limiter": "vanleer", "riemann": "hlld", "emf": "uct_hll",
                    "integrator": "ssp_rk2", "cfl": 0.3, "precision": "fp64"},
         "hbm_roofline_frac_step": value * 1e6 * STEP_BYTES / HBM_PEAK,
+        "step_bytes_per_cell": {"algorithmic": STEP_BYTES, "counted": STEP_TRAFFIC["fp64"]},
         "physical": physical,
         "roofline": roofline,
         "kernels": kernels,
@@ -320,6 +325,8 @@ def main(argv=None):
         vm = ncell * args.steps / el_m / 1e6
         out["mixed"] = {"value": vm, "unit": "Mcell-updates/s", "ms_per_step": el_m / args.steps * 1e3,
                         "hbm_roofline_frac_step": vm * 1e6 * STEP_BYTES / HBM_PEAK,
+                        "step_bytes_per_cell": {"algorithmic": STEP_BYTES,
+                                                "counted": STEP_TRAFFIC["mixed"]},
                         "roofline": face_roofline(kt_m, ncell, "mixed"),
                         "physical": phys_m,
                         "config": {"workload": "turbulence_3d_lowbeta_%d" % args.n, "mach": 3,
