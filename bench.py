@@ -168,6 +168,41 @@ def time_adjoint_blast(n, nsteps, every, integrator="rk2"):
     return _time_backward(AD, ctx, U0, dts, every)
 
 
+def time_2d_graph(n=128, steps=100, per_graph=10):
+    """The 2D Orszag-Tang configuration, 128^2: microseconds per step run
+    eagerly (one library call per step, each some ten kernel launches on
+    16 K cells: launch-bound) and with per_graph steps captured in a HIP graph
+    (torch.cuda.CUDAGraph) that is replayed."""
+    import torch
+    from paper_2511_20337_amd import mhd, workloads as W
+    dev = torch.device("cuda:0")
+    s, U0 = W.orszag_tang_2d(n)
+    ctx = mhd.Context(s, dev)
+    U = torch.from_numpy(U0).to(dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(5):
+        ctx.step_cfl(U, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step_cfl(U, dt)
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / steps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(per_graph):
+            ctx.step_cfl(U, dt)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // per_graph):
+        g.replay()
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / (steps // per_graph * per_graph)
+    return {"workload": "orszag_tang_2d_%d" % n, "us_per_step_eager": eager * 1e6,
+            "us_per_step_graph": graph * 1e6, "steps": steps, "steps_per_graph": per_graph}
+
+
 def cpu_baseline(n_sample: int, setup_fn, steps: int = 2):
     """The oracle, untuned, on the same generator at n_sample^3: `steps` steps
     (CFL dt + RK2 step each) with every host thread this process may use."""
@@ -237,6 +272,8 @@ def only_part(part, n, steps, warmup):
                "workload": "turbulence_3d_%d glm" % n, "physical": phys,
                "ms_per_step": el / steps * 1e3,
                "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt.items() if v[1]}}
+    elif part == "ot2d_graph":
+        out = dict({"part": part}, **time_2d_graph())
     elif part == "adjoint":
         adj, fwd = time_adjoint(512, 64, 8)
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
@@ -264,8 +301,8 @@ def main(argv=None):
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters) and exit")
-    ap.add_argument("--only", choices=("mixed", "ot3d_wenoz", "glm", "adjoint", "adjoint_3d",
-                                       "adjoint_3d_rk3"), default=None,
+    ap.add_argument("--only", choices=("mixed", "ot3d_wenoz", "glm", "ot2d_graph", "adjoint",
+                                       "adjoint_3d", "adjoint_3d_rk3"), default=None,
                     help="run only this extra measurement and print it (for profiling)")
     args = ap.parse_args(argv)
     if args.copy_probe:
@@ -333,11 +370,12 @@ def main(argv=None):
                                    "beta": 0.01, "precision": "mixed"},
                         "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_m.items() if v[1]}}
         out["large"] = {}
-        for name, fn, n in (("turbulence_3d_lowbeta_384", W.turbulence_3d_lowbeta, 384),
-                            ("blast_3d_640", W.blast_3d, 640)):
-            log("mixed precision, large grid: %s" % name)
+        # the step counts these workloads are named with (C3: 50 steps at 384^3;
+        # C5: 100 steps of the blast at 640^3)
+        for name, fn, n, steps_l in (("turbulence_3d_lowbeta_384", W.turbulence_3d_lowbeta, 384, 50),
+                                     ("blast_3d_640", W.blast_3d, 640, 100)):
+            log("mixed precision, large grid: %s, %d steps" % (name, steps_l))
             sl, Ul = fn(n)
-            steps_l = max(1, args.steps // 5)
             el_l, kt_l, _, phys_l = time_gpu(sl, Ul, steps_l, 1)
             del Ul
             vl = n ** 3 * steps_l / el_l / 1e6
@@ -390,6 +428,8 @@ def main(argv=None):
                       "config": {"workload": "turbulence_3d_%d" % args.n, "divb": "glm",
                                  "limiter": "vanleer", "riemann": "hlld", "integrator": "ssp_rk2"},
                       "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_g.items() if v[1]}}
+        log("2D Orszag-Tang 128^2: eager steps and steps replayed from a HIP graph")
+        out["orszag_tang_2d"] = time_2d_graph()
         log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, checkpoints every 8")
         adj, fwd = time_adjoint(512, 64, 8)
         out["adjoint"] = {"value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,

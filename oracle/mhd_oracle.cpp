@@ -288,6 +288,7 @@ template <class R> R fast_speed(R g, R rho, R p, R bn, R bt1, R bt2) {
 // Diagnostic counters of the HLLD degeneracy test (star sides evaluated,
 // sides found degenerate), per working precision: [0] FP64, [1] FP32.
 long long g_deg_sides[2], g_deg_hits[2];
+bool g_count_deg = false;  // set only while oracle_count_degenerate runs
 template <class R> constexpr int prec_index() { return std::is_same<R, float>::value ? 1 : 0; }
 
 // Relative tolerance of the HLLD degeneracy test, per working precision.
@@ -382,11 +383,15 @@ void riemann(int solver, R g, const R wl[7], const R wr[7], R bn, RSOut<R>& o,
     // unchanged when |D| is within a relative tolerance of 1e-12 in FP64
     // units, scaled to the working precision (x 2^29 in FP32)
     const bool degenerate = Abs(D) <= R(DegTol<R>::value) * (Abs(big) + bn * bn);
+    if (g_count_deg) {
 #pragma omp atomic
-    g_deg_sides[prec_index<R>()] += 1;
+      g_deg_sides[prec_index<R>()] += 1;
+      if (degenerate) {
+#pragma omp atomic
+        g_deg_hits[prec_index<R>()] += 1;
+      }
+    }
     if (degenerate) {
-#pragma omp atomic
-      g_deg_hits[prec_index<R>()] += 1;
       vs[s] = w[2]; ws[s] = w[3]; b1s[s] = w[4]; b2s[s] = w[5];
       zeta[s] = R(1);
       eta[s] = R(0);
@@ -1060,6 +1065,7 @@ int oracle_count_degenerate(const OCfg* cfg, const double* U, long long* out) {
   if (!cfg_ok(cfg) || !U || !out) return -1;
   const Grid G(*cfg);
   std::vector<double> L((size_t)NF * G.ncell);
+  g_count_deg = true;
   for (int p = 0; p < 2; ++p) {
     OCfg c = *cfg;
     c.precision = p;
@@ -1068,6 +1074,7 @@ int oracle_count_degenerate(const OCfg* cfg, const double* U, long long* out) {
     out[2 * p] = g_deg_sides[p];
     out[2 * p + 1] = g_deg_hits[p];
   }
+  g_count_deg = false;
   return 0;
 }
 
