@@ -42,7 +42,7 @@ def oracle_at_samples(setup, U0, dts, centres, radius=None):
     m = 2 * radius + 1
     sp = W.make_setup("patch", 3, m, m, m, (0, m * dx, 0, m * dy, 0, m * dz), setup["gamma"],
                       setup["cfl"], setup["limiter"], setup["riemann"], setup["precision"])
-    sp = dict(sp, integrator=setup.get("integrator", "rk2"))
+    sp = dict(sp, integrator=setup.get("integrator", "rk2"), emf=setup.get("emf", "uct_hll"))
     c = O.cfg_from(sp)
     out = []
     for (k, j, i) in centres:

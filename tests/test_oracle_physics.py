@@ -383,11 +383,13 @@ def test_mixed_precision_close_to_fp64():
     assert np.abs(O.divb(cmx, Umx)).max() / np.abs(Umx[5:]).max() / 16 < 1e-12
 
 
-def test_patch_sampling_reproduces_full_grid():
+@pytest.mark.parametrize("emf", ["uct_hll", "uct_hlld"])
+def test_patch_sampling_reproduces_full_grid(emf):
     """The sampled-cell oracle used for full-size GPU checks equals the oracle
-    on the whole grid, bit for bit, over two steps."""
+    on the whole grid, bit for bit, over two steps (with either edge average)."""
     from tests.oracle_patches import oracle_at_samples
     s, U0 = W.turbulence_3d(32)
+    s = dict(s, emf=emf)
     c = O.cfg_from(s)
     d0 = O.dt(c, U0)
     U1 = O.step(c, U0, d0)
