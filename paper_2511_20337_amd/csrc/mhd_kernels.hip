@@ -662,39 +662,47 @@ __global__ __launch_bounds__(kBlock) void k_faces_weno(const double* __restrict_
 // 3D face kernel marching along z. A workgroup owns a 64 x 4 column of cells
 // and walks a run of planes k0 <= k < k1, one cell of each plane per thread.
 // LDS holds the primitives of planes k-1, k, k+1 of the column (a ring of
-// three), the x/y cross halo (two cells below, one above) of plane k, and
-// B_z of planes k and k+1 (only the x/y faces of plane k need it). The lower
-// z-face of cell k takes its left state V_{k-1} + slope_{k-1}/2 from the
-// previous plane's step, where the thread computed slope_{k-1} for the right
-// state of the face below; each z slope is thus evaluated once. Per plane only
-// the core of plane k+2 and the halo of plane k+1 are recovered; the raw state
-// of the own cell of plane k+2 is loaded before the faces of plane k are
-// solved, so its latency hides behind them. (Measured at 256^3: 64 x 4
-// columns beat 16 x 16 ones, and dealing x-neighbour columns to one XCD is
-// slower than the natural order.)
+// three) and the x/y cross halo (two cells below, one above) of planes k and
+// k+1 (two buffers). The lower z-face of cell k takes its left state
+// V_{k-1} + slope_{k-1}/2 from the previous plane's step, where the thread
+// computed slope_{k-1} for the right state of the face below; each z slope is
+// thus evaluated once. Per plane only the core of plane k+2 and the halo of
+// plane k+1 are recovered. Their raw values are loaded before any face of
+// plane k is solved, so that their latency hides behind the solves, and
+// waiting for them never waits for the face records stored after them (the
+// vector-memory counter retires in issue order); the normal fields of the
+// faces come from raw cells loaded two planes earlier. Neighbours read only
+// plane k of the ring and the current halo buffer, and a thread alone reads
+// its own cells of planes k-1 and k+1, so the recovered plane k+2 (into the
+// slot of plane k-1) and the halo of plane k+1 (into the other buffer) are
+// written without waiting, and one barrier per plane publishes them.
+// (Measured at 256^3 in FP64: 1.53 ms per launch against 1.65 ms for the
+// same arithmetic with the loads issued after the records of the plane and
+// two barriers per plane; 64 x 4 columns beat 16 x 16 ones, and dealing
+// x-neighbour columns to one XCD is slower than the natural order.)
 struct March {
   static constexpr int TX = 64, TY = 4, NCORE = TX * TY;
   static constexpr int NHALO = 3 * TY + 3 * TX;  // x-halo then y-halo
-  static constexpr int NQ = 7;                   // ring quantities: V slots 0..6
+  static constexpr int NQ = 8;                   // primitives per cell: V slots 0..7
 };
 static_assert(March::NCORE == kBlock, "one column cell per thread");
-
+static_assert(March::NHALO <= March::NCORE, "at most one halo cell per thread");
 
 // Planes per run: the prologue costs two extra planes per run, shorter runs
 // give more workgroups (4096 at 256^3 with 16; 16 measured faster than 32).
 constexpr int kMarchRun = 16;
 
+// 73.5 KB in FP64: two workgroups (eight waves) per CU.
 template <class R>
 struct MarchLds {
-  R ring[3][March::NQ][March::NCORE];  // planes by (k - kbase) % 3
-  R bz[2][March::NCORE];               // B_z (slot 7) of planes by (k - kbase) & 1
-  R halo[8][March::NHALO];             // x/y halo of the current plane
+  R ring[3][March::NQ][March::NCORE];   // planes by (k - k0 + 1) % 3
+  R halo[2][March::NQ][March::NHALO];   // planes by (k - k0) & 1
 };
-// flat offsets (in R) of the three parts
-constexpr int kRingQ = March::NCORE;                          // quantity stride in the ring
-constexpr int kRingP = March::NQ * March::NCORE;              // plane stride in the ring
-constexpr int kBzOff = 3 * kRingP;
-constexpr int kHaloOff = kBzOff + 2 * March::NCORE;
+// flat offsets (in R) of the parts
+constexpr int kRingQ = March::NCORE;              // quantity stride in the ring
+constexpr int kRingP = March::NQ * March::NCORE;  // plane stride in the ring
+constexpr int kHaloOff = 3 * kRingP;
+constexpr int kHaloB = March::NQ * March::NHALO;  // halo buffer stride
 
 // Position of halo entry h of a plane, relative to the column origin;
 // s = 0, 1, 2: two cells below the column, then one above.
@@ -711,83 +719,134 @@ __device__ __forceinline__ void march_halo_pos(int h, int& x, int& y) {
   }
 }
 
-// Primitives (FP64 recovery, rounded to R) of cell (i,j,k), indices wrapped.
-template <class R>
-__device__ __forceinline__ bool march_prim(const double* __restrict__ U, const Geom& g, int i,
-                                           int j, int k, R* V) {
-  double W[8];
-  const bool ok = prim_at<3>(U, g, wrap_any(i, g.nx), wrap_any(j, g.ny), wrap_any(k, g.nz), W);
+// Byte offsets within a plane of one field (FP64) of the values the primitive
+// recovery of cell (i, j) reads (indices wrapped): the cell, and its upper x
+// and y neighbours (staggered B_x, B_y). The staggered B_z above is the
+// cell's own offset in the next plane. 32 bits: a plane holds fewer than
+// 2^29 cells.
+struct PlaneOffs {
+  uint32_t c, xp, yp;
+};
+__device__ __forceinline__ PlaneOffs plane_offs(const Geom& g, int i, int j) {
+  const int iw = wrap_any(i, g.nx), jw = wrap_any(j, g.ny);
+  PlaneOffs p;
+  p.c = (uint32_t)(jw * g.nx + iw) * 8u;
+  p.xp = (uint32_t)(jw * g.nx + wrap(iw + 1, g.nx)) * 8u;
+  p.yp = (uint32_t)(wrap(jw + 1, g.ny) * g.nx + iw) * 8u;
+  return p;
+}
+// The value at byte offset off of the uniform base b.
+__device__ __forceinline__ double ld_at(const double* __restrict__ b, uint32_t off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(b) + off);
+}
+// Raw values of the cell at offsets p in plane kw; the staggered B_z above
+// from plane kw1 (both wrapped into 0..nz-1).
+__device__ __forceinline__ RawCell load_raw_plane(const double* __restrict__ U, const Geom& g,
+                                                  int64_t nxy, int kw, int kw1,
+                                                  const PlaneOffs& p) {
+  const double* pl = U + kw * nxy;
+  RawCell r;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) V[q] = (R)W[q];
+  for (int q = 0; q < 8; ++q) r.u[q] = ld_at(pl + q * g.n, p.c);
+  r.bxp = ld_at(pl + 5 * g.n, p.xp);
+  r.byp = ld_at(pl + 6 * g.n, p.yp);
+  r.bzp = ld_at(U + 7 * g.n + kw1 * nxy, p.c);
+  return r;
+}
+
+// Primitives of a raw cell (FP64 recovery) rounded to R, into LDS at lds[o]
+// with quantity stride st.
+template <class R>
+__device__ __forceinline__ bool march_recover(const RawCell& raw, double gamma, R* lds, int o,
+                                              int st, double* W) {
+  const bool ok = prim_from_raw<3>(raw, gamma, W);
+#pragma unroll
+  for (int q = 0; q < March::NQ; ++q) lds[o + q * st] = (R)W[q];
   return ok;
 }
 
-// Store a core cell's primitives: slots 0..6 in ring plane rp, B_z in bz
-// plane bp (bp < 0: B_z not kept).
-template <class R>
-__device__ __forceinline__ void march_put_core(R* lds, int rp, int bp, int cidx, const R* V) {
-#pragma unroll
-  for (int q = 0; q < March::NQ; ++q) lds[rp * kRingP + q * kRingQ + cidx] = V[q];
-  if (bp >= 0) lds[kBzOff + bp * March::NCORE + cidx] = V[7];
-}
-
 // Offsets of plane-k cell (xx, yy) (at most one coordinate outside the
-// column): quantity q < 7 at lds[o + q * st], B_z at lds[ob].
-__device__ __forceinline__ void march_xy(int rp, int bp, int xx, int yy, int& o, int& st,
-                                         int& ob) {
+// column): quantity q at lds[o + q * st]; r is the ring plane of k, hb its
+// halo buffer.
+__device__ __forceinline__ void march_xy(int r, int hb, int xx, int yy, int& o, int& st) {
   if (xx < 0 || xx >= March::TX || yy < 0 || yy >= March::TY) {
     const int h = (xx < 0 || xx >= March::TX)
                       ? ((xx < 0) ? xx + 2 : 2) * March::TY + yy
                       : 3 * March::TY + ((yy < 0) ? yy + 2 : 2) * March::TX + xx;
-    o = kHaloOff + h;
+    o = kHaloOff + hb * kHaloB + h;
     st = March::NHALO;
-    ob = kHaloOff + 7 * March::NHALO + h;
   } else {
-    const int c = yy * March::TX + xx;
-    o = rp * kRingP + c;
+    o = r * kRingP + yy * March::TX + xx;
     st = kRingQ;
-    ob = kBzOff + bp * March::NCORE + c;
   }
 }
 
-// Writes the nine records of a lower face from its reconstructed states.
-template <int D, int RS, class R, int EM>
-__device__ __forceinline__ void march_solve(const R* wl, const R* wr, R bn,
-                                            double* __restrict__ FW, const Geom& g, int64_t c) {
-  RiemannOut<R> o;
-  riemann<RS, R, EM>((R)g.gamma, wl, wr, bn, o);
-  put_record<3, D, EM, R>(FW, g.n, c, o);
+// Writes the nine records of a lower face of the plane whose records start
+// at fwp (slot 0 of direction 0), the cell at byte offset boff.
+template <int D, int EM, class R>
+__device__ __forceinline__ void put_record_at(R* __restrict__ fwp, int64_t n, uint32_t boff,
+                                              const RiemannOut<R>& o) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  auto put = [&](int slot, R v) {
+    *reinterpret_cast<R*>(reinterpret_cast<char*>(fwp + ((int64_t)D * NSLOT + slot) * n) +
+                          boff) = v;
+  };
+  put(S_RHO, o.f[0]);
+  put(S_MX + D, o.f[1]);
+  put(S_MX + T1, o.f[2]);
+  put(S_MX + T2, o.f[3]);
+  put(S_EN, o.f[6]);
+  if (EM == 1) {
+    put(S_AP, o.om);
+    put(S_AM, o.dl);
+    put(S_DR, o.dr);
+  } else {
+    put(S_AP, o.ap);
+    put(S_AM, o.am);
+  }
+  put(S_V1, o.v1);
+  put(S_V2, o.v2);
 }
 
-// Lower x (D = 0) or y (D = 1) face of a cell of plane k: PLM over the four
-// stencil cells (offsets o*, strides s*, B_z offsets b*), then the solver.
-template <int D, int LIM, int RS, class R, int EM>
-__device__ __forceinline__ void march_face_xy(const R* lds, const int* o, const int* st,
-                                              const int* ob, R bn,
-                                              double* __restrict__ FW, const Geom& g, int64_t c) {
+template <int D, int RS, class R, int EM>
+__device__ __forceinline__ void march_solve(const R* wl, const R* wr, R bn, R gamma,
+                                            R* __restrict__ fwp, int64_t n, uint32_t boff) {
+  RiemannOut<R> o;
+  riemann<RS, R, EM>(gamma, wl, wr, bn, o);
+  put_record_at<D, EM, R>(fwp, n, boff, o);
+}
+
+// Reconstructed states of the lower x (D = 0) or y (D = 1) face of a cell of
+// plane k: PLM over the four stencil cells (offsets o*, strides s*).
+template <int D, int LIM, class R>
+__device__ __forceinline__ void march_recon_xy(const R* lds, const int* o, const int* st, R* wl,
+                                               R* wr) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   constexpr int slot[7] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4};
-  R wl[7], wr[7];
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
     const int sq = slot[q];
     R v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = (sq == 7) ? lds[ob[s]] : lds[o[s] + sq * st[s]];
+    for (int s = 0; s < 4; ++s) v[s] = lds[o[s] + sq * st[s]];
     wl[q] = fma_r(R(0.5), plm_slope<LIM, R>(v[1] - v[0], v[2] - v[1]), v[1]);
     wr[q] = fma_r(R(-0.5), plm_slope<LIM, R>(v[2] - v[1], v[3] - v[2]), v[2]);
   }
-  march_solve<D, RS, R, EM>(wl, wr, bn, FW, g, c);
 }
 
 // cflp != nullptr: also the CFL bound of the state, reduced over the cells
 // of this workgroup's column and run (each cell is the own cell of exactly
 // one workgroup and plane) into cflp[blockIdx.x]; k_cfl_final finishes it.
-template <int LIM, int RS, class R, int EM>
+// FULL: every column lies inside the grid (nx % 64 == 0, ny % 4 == 0), so no
+// thread skips the faces. Then every path through a plane issues the same
+// loads and stores, and the waits for the prefetched cells count exactly the
+// stores issued after them (no skipped-faces path forces waiting for the
+// stores as well).
+template <int LIM, int RS, class R, int EM, bool FULL>
 __global__ __launch_bounds__(kBlock)
 void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g, MarchGrid mg,
                    int* __restrict__ flag, double* __restrict__ cflp) {
-  // slots of the z-face frame (rho, v_z, v_x, v_y, B_x, B_y, p): all in the ring
+  // slots of the z-face frame (rho, v_z, v_x, v_y, B_x, B_y, p)
   constexpr int zslot[7] = {0, 3, 1, 2, 5, 6, 4};
   __shared__ MarchLds<R> L;
   R* lds = &L.ring[0][0][0];
@@ -799,79 +858,96 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
   const int i0 = tx * March::TX, j0 = ty * March::TY;
   const int k0 = zc * mg.lz;
   const int k1 = min(k0 + mg.lz, g.nz);
-  const int kbase = k0 - 1;  // ring plane of absolute k: (k - kbase) % 3
   const int x = (int)threadIdx.x % March::TX, y = (int)threadIdx.x / March::TX;
   const int cidx = y * March::TX + x;
   const int i = i0 + x, j = j0 + y;
-  const bool inside = (i < g.nx) && (j < g.ny);
-  int hx = 0, hy = 0;
+  const bool inside = FULL || ((i < g.nx) && (j < g.ny));
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+  const R gam = (R)g.gamma;
+  // own cell; halo cell (threads past the halo load a valid cell and drop it)
+  const PlaneOffs po = plane_offs(g, i, j);
   const bool haloer = (int)threadIdx.x < March::NHALO;
-  if (haloer) march_halo_pos((int)threadIdx.x, hx, hy);
+  int hx, hy;
+  march_halo_pos(haloer ? (int)threadIdx.x : March::NHALO - 1, hx, hy);
+  const PlaneOffs ph = plane_offs(g, i0 + hx, j0 + hy);
   bool bad = false;
-  // prologue: own cells of planes k0-2 .. k0+1; ring gets k0-1 .. k0+1,
-  // B_z of k0 and k0+1, halo of plane k0; the left state of the first z-face.
+  // Prologue: own cells of planes k0-2 .. k0+1, the ring gets k0-1, k0,
+  // k0+1 (slots 0, 1, 2), halo buffer 0 the halo of plane k0; the left state
+  // of the first z-face. The staggered normal fields of the own cell (the
+  // raw B of its lower faces) of planes k and k+1 are carried in registers:
+  // each plane's are taken from the raw cell loaded two planes earlier.
   R zl[7];
   double cmin = __builtin_inf();  // CFL bound over this thread's own cells
+  double bn0[3], bn1[3];          // normal fields of planes k, k+1
   {
-    R Vm2[8], Vm1[8], V0[8], Vp1[8];
-    bad |= !march_prim<R>(U, g, i, j, k0 - 2, Vm2);
-    bad |= !march_prim<R>(U, g, i, j, k0 - 1, Vm1);
-    {
-      double W[8];
-      bad |= !prim_at<3>(U, g, wrap_any(i, g.nx), wrap_any(j, g.ny), wrap_any(k0, g.nz), W);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) V0[q] = (R)W[q];
-      if (cflp && inside) cmin = cfl_bound(g, W, cmin);
-      bad |= !prim_at<3>(U, g, wrap_any(i, g.nx), wrap_any(j, g.ny), wrap_any(k0 + 1, g.nz), W);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) Vp1[q] = (R)W[q];
-      if (cflp && inside && k0 + 1 < k1) cmin = cfl_bound(g, W, cmin);
-    }
-    march_put_core<R>(lds, 0, -1, cidx, Vm1);  // k0-1: ring 0 (its B_z is not needed)
-    march_put_core<R>(lds, 1, 1, cidx, V0);    // k0: ring 1, bz (k0 - kbase) & 1 = 1
-    march_put_core<R>(lds, 2, 0, cidx, Vp1);   // k0+1: ring 2, bz 0
+    const int km2 = wrap_any(k0 - 2, g.nz), km1 = wrap_any(k0 - 1, g.nz);
+    const int kp1 = wrap_any(k0 + 1, g.nz), kp2 = wrap_any(k0 + 2, g.nz);
+    double Wm2[8], Wm1[8], W[8];
+    bad |= !prim_from_raw<3>(load_raw_plane(U, g, nxy, km2, km1, po), g.gamma, Wm2);
+    bad |= !march_recover<R>(load_raw_plane(U, g, nxy, km1, k0, po), g.gamma, lds,
+                             0 * kRingP + cidx, kRingQ, Wm1);
+    R zm2[7], zm1[7];
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-      const int sq = zslot[q];
-      zl[q] = fma_r(R(0.5), plm_slope<LIM, R>(Vm1[sq] - Vm2[sq], V0[sq] - Vm1[sq]), Vm1[sq]);
+      zm2[q] = (R)Wm2[zslot[q]];
+      zm1[q] = (R)Wm1[zslot[q]];
     }
-    if (haloer) {
-      R H[8];
-      bad |= !march_prim<R>(U, g, i0 + hx, j0 + hy, k0, H);
+    const RawCell c0 = load_raw_plane(U, g, nxy, k0, kp1, po);
+    bad |= !march_recover<R>(c0, g.gamma, lds, 1 * kRingP + cidx, kRingQ, W);
+    if (cflp && inside) cmin = cfl_bound(g, W, cmin);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) lds[kHaloOff + q * March::NHALO + threadIdx.x] = H[q];
+    for (int q = 0; q < 7; ++q)
+      zl[q] = fma_r(R(0.5), plm_slope<LIM, R>(zm1[q] - zm2[q], (R)W[zslot[q]] - zm1[q]), zm1[q]);
+    const RawCell c1 = load_raw_plane(U, g, nxy, kp1, kp2, po);
+    bad |= !march_recover<R>(c1, g.gamma, lds, 2 * kRingP + cidx, kRingQ, W);
+    if (cflp && inside && k0 + 1 < k1) cmin = cfl_bound(g, W, cmin);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      bn0[d] = c0.u[5 + d];
+      bn1[d] = c1.u[5 + d];
     }
+    if (haloer)
+      bad |= !march_recover<R>(load_raw_plane(U, g, nxy, k0, kp1, ph), g.gamma, lds,
+                               kHaloOff + (int)threadIdx.x, March::NHALO, W);
   }
   __syncthreads();
+  int rm = 0, r0 = 1, rp = 2, hb = 0;
+  R* const fw0 = stored<R>(FW);
+  const uint32_t boff = (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(R);  // valid when inside
   for (int k = k0; k < k1; ++k) {
-    const int rm = (k - 1 - kbase) % 3, r0 = (k - kbase) % 3, rp = (k + 1 - kbase) % 3;
-    const int b0 = (k - kbase) & 1;
     const bool more = k + 1 < k1;
-    // normal fields of this cell's faces, then the raw state of the own cell
-    // of plane k+2, in flight while the faces are solved
-    const int64_t c = lin(g, i, j, k);
-    double bnx = 0.0, bny = 0.0, bnz = 0.0;
+    // The raw halo cell of plane k+1 and the raw own cell of plane k+2,
+    // loaded by every thread (in-bounds, wrapped indices) before any face
+    // record of this plane is stored.
+    const int ka = wrap_any(k + 1, g.nz), kb = wrap_any(k + 2, g.nz), kc = wrap_any(k + 3, g.nz);
+    const RawCell hr = load_raw_plane(U, g, nxy, ka, kb, ph);
+    const RawCell nxt = load_raw_plane(U, g, nxy, kb, kc, po);
+    R* const fwp = fw0 + k * nxy;
+    R wl[7], wr[7];
+    int o[4], st[4];
     if (inside) {
-      bnx = U[5 * g.n + c];
-      bny = U[6 * g.n + c];
-      bnz = U[7 * g.n + c];
+      march_xy(r0, hb, x - 2, y, o[0], st[0]);
+      march_xy(r0, hb, x - 1, y, o[1], st[1]);
+      march_xy(r0, hb, x, y, o[2], st[2]);
+      march_xy(r0, hb, x + 1, y, o[3], st[3]);
+      march_recon_xy<0, LIM, R>(lds, o, st, wl, wr);
     }
-    RawCell nxt;
-    if (more) nxt = load_raw<3>(U, g, wrap_any(i, g.nx), wrap_any(j, g.ny), wrap_any(k + 2, g.nz));
+    // the halo of plane k+1 into the other buffer (read by no one before the
+    // barrier below), once the x reconstruction has covered its latency
+    if (more && haloer) {
+      double W[8];
+      bad |= !march_recover<R>(hr, g.gamma, lds, kHaloOff + (hb ^ 1) * kHaloB + (int)threadIdx.x,
+                               March::NHALO, W);
+    }
     if (inside) {
-      int o[4], st[4], ob[4];
-      march_xy(r0, b0, x - 2, y, o[0], st[0], ob[0]);
-      march_xy(r0, b0, x - 1, y, o[1], st[1], ob[1]);
-      march_xy(r0, b0, x, y, o[2], st[2], ob[2]);
-      march_xy(r0, b0, x + 1, y, o[3], st[3], ob[3]);
-      march_face_xy<0, LIM, RS, R, EM>(lds, o, st, ob, (R)bnx, FW, g, c);
-      march_xy(r0, b0, x, y - 2, o[0], st[0], ob[0]);
-      march_xy(r0, b0, x, y - 1, o[1], st[1], ob[1]);
-      march_xy(r0, b0, x, y + 1, o[3], st[3], ob[3]);
-      march_face_xy<1, LIM, RS, R, EM>(lds, o, st, ob, (R)bny, FW, g, c);
+      march_solve<0, RS, R, EM>(wl, wr, (R)bn0[0], gam, fwp, g.n, boff);
+      march_xy(r0, hb, x, y - 2, o[0], st[0]);
+      march_xy(r0, hb, x, y - 1, o[1], st[1]);
+      march_xy(r0, hb, x, y + 1, o[3], st[3]);
+      march_recon_xy<1, LIM, R>(lds, o, st, wl, wr);
+      march_solve<1, RS, R, EM>(wl, wr, (R)bn0[1], gam, fwp, g.n, boff);
       // z face: left state carried from the plane below; the slope of cell k
       // gives the right state and the next plane's left state
-      R wl[7], wr[7];
 #pragma unroll
       for (int q = 0; q < 7; ++q) {
         const int sq = zslot[q];
@@ -883,25 +959,26 @@ void k_faces_march(const double* __restrict__ U, double* __restrict__ FW, Geom g
         wr[q] = fma_r(R(-0.5), dlt, bb);
         zl[q] = fma_r(R(0.5), dlt, bb);
       }
-      march_solve<2, RS, R, EM>(wl, wr, (R)bnz, FW, g, c);
+      march_solve<2, RS, R, EM>(wl, wr, (R)bn0[2], gam, fwp, g.n, boff);
     }
     if (more) {
-      __syncthreads();  // plane k-1, B_z of plane k and the halo of plane k are free
+      // plane k+2 into the ring slot of plane k-1 (own cell, read by no
+      // other thread)
       double W[8];
-      bad |= !prim_from_raw<3>(nxt, g.gamma, W);
+      bad |= !march_recover<R>(nxt, g.gamma, lds, rm * kRingP + cidx, kRingQ, W);
       if (cflp && inside && k + 2 < k1) cmin = cfl_bound(g, W, cmin);
-      R V[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) V[q] = (R)W[q];
-      march_put_core<R>(lds, rm, b0, cidx, V);  // plane k+2: ring (k+2-kbase)%3 == rm
-      if (haloer) {
-        R H[8];
-        bad |= !march_prim<R>(U, g, i0 + hx, j0 + hy, k + 1, H);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) lds[kHaloOff + q * March::NHALO + threadIdx.x] = H[q];
+      for (int d = 0; d < 3; ++d) {
+        bn0[d] = bn1[d];
+        bn1[d] = nxt.u[5 + d];
       }
       __syncthreads();
     }
+    const int t = rm;
+    rm = r0;
+    r0 = rp;
+    rp = t;
+    hb ^= 1;
   }
   if (cflp) workgroup_min_store(cmin, cflp + blockIdx.x);
   if (bad) atomicOr(flag, 1);
@@ -1224,9 +1301,16 @@ hipError_t stage_impl(const StageArgs& a) {
                                  a.PW, a.U, a.FW, a.g));
   } else if constexpr (DIM == 3) {
     const MarchGrid mg = march_grid(a.g);
-    MHD_TIMED(a, K_FACES,
-              hipLaunchKernelGGL((k_faces_march<LIM, RS, R, EM>), dim3(mg.nblocks), dim3(kBlock), 0,
-                                 a.stream, a.U, a.FW, a.g, mg, a.flag, a.cfl_partial));
+    if (a.g.nx % March::TX == 0 && a.g.ny % March::TY == 0)
+      MHD_TIMED(a, K_FACES,
+                hipLaunchKernelGGL((k_faces_march<LIM, RS, R, EM, true>), dim3(mg.nblocks),
+                                   dim3(kBlock), 0, a.stream, a.U, a.FW, a.g, mg, a.flag,
+                                   a.cfl_partial));
+    else
+      MHD_TIMED(a, K_FACES,
+                hipLaunchKernelGGL((k_faces_march<LIM, RS, R, EM, false>), dim3(mg.nblocks),
+                                   dim3(kBlock), 0, a.stream, a.U, a.FW, a.g, mg, a.flag,
+                                   a.cfl_partial));
     if (a.cfl_partial)  // dt of the state U, before the update kernels read it
       MHD_TIMED(a, K_CFL_FINAL,
                 hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, a.cfl_partial,
