@@ -516,18 +516,16 @@ __device__ __forceinline__ void edge_to_face(const double* __restrict__ U,
   const double* e = EB + (int64_t)C * NE * n;
   const int64_t cm1 = shifted<E>(g, i, j, k, -1), cp1 = shifted<E>(g, i, j, k, 1);
   const int64_t cm2 = shifted<E>(g, i, j, k, -2), cp2 = shifted<E>(g, i, j, k, 2);
-  // alpha: the edge at c takes max(face c-e, face c); the edge at c+e takes
-  // max(face c, face c+e); the first argument wins ties.
-  {
-    const double* ap = f + S_AP * n;
-    const double* am = f + S_AM * n;
-    if (ap[c] > ap[cm1]) apbar += e[sap * n + c];
-    if (!(ap[cp1] > ap[c])) apbar += e[sap * n + cp1];
-    if (am[c] > am[cm1]) ambar += e[sam * n + c];
-    if (!(am[cp1] > am[c])) ambar += e[sam * n + cp1];
-  }
-  // reconstructed values: upper extrapolation of face p feeds the edge at
-  // p+e (as its lower value), the lower extrapolation feeds the edge at p
+  // Every value is loaded before any comparison, so that the loads go out
+  // together instead of one round trip per taken branch; the empty asm keeps
+  // the compiler from sinking the four alpha cotangent loads back into the
+  // branches that add them.
+  const double* ap = f + S_AP * n;
+  const double* am = f + S_AM * n;
+  const double apm = ap[cm1], ap0 = ap[c], app = ap[cp1];
+  const double amm = am[cm1], am0 = am[c], amp = am[cp1];
+  double ea0 = e[sap * n + c], eap = e[sap * n + cp1];
+  double em0 = e[sam * n + c], emp = e[sam * n + cp1];
   const double* v = f + (ROLE == 0 ? S_V1 : S_V2) * n;
   const double* b = U + (F_BX + D) * n;
   const double xv[5] = {v[cm2], v[cm1], v[c], v[cp1], v[cp2]};
@@ -536,6 +534,15 @@ __device__ __forceinline__ void edge_to_face(const double* __restrict__ U,
   const double vm[3] = {e[svhi * n + cm1], e[svhi * n + c], e[svhi * n + cp1]};
   const double bp[3] = {e[sblo * n + c], e[sblo * n + cp1], e[sblo * n + cp2]};
   const double bm[3] = {e[sbhi * n + cm1], e[sbhi * n + c], e[sbhi * n + cp1]};
+  asm volatile("" : "+v"(ea0), "+v"(eap), "+v"(em0), "+v"(emp));
+  // alpha: the edge at c takes max(face c-e, face c); the edge at c+e takes
+  // max(face c, face c+e); the first argument wins ties.
+  apbar = (ap0 > apm) ? apbar + ea0 : apbar;
+  apbar = !(app > ap0) ? apbar + eap : apbar;
+  ambar = (am0 > amm) ? ambar + em0 : ambar;
+  ambar = !(amp > am0) ? ambar + emp : ambar;
+  // reconstructed values: upper extrapolation of face p feeds the edge at
+  // p+e (as its lower value), the lower extrapolation feeds the edge at p
   vbar += plm_adjoint<LIM>(xv, vp, vm);
   bbar += plm_adjoint<LIM>(xb, bp, bm);
 }
