@@ -324,23 +324,43 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
     d[0] = by[cp]; d[1] = bx[cp];
     d[2] = bz[cjm2]; d[3] = bz[cjm1]; d[4] = bz[c]; d[5] = bz[cjp1];
     d[6] = bz[cim2]; d[7] = bz[cim1]; d[8] = bz[cip1];
+    // E_z: (A, B) = (x, y); its inputs are loaded here too, so that no load
+    // of the plane is issued after one of its EMF stores (the wait for it
+    // would then wait for the store as well)
+    const FaceCoef<EM, R> xjm = face_coef<EM, R>(fx, n, cjm1);
+    const FaceCoef<EM, R> yim = face_coef<EM, R>(fy, n, cim1);
+    const R* vyx = fy + S_V2 * n;  // v_x on y-faces
+    const R* vxy = fx + S_V1 * n;  // v_y on x-faces
+    const R zwv[4] = {vyx[cim2], vyx[cim1], vyx[c], vyx[cip1]};
+    const R zsv[4] = {vxy[cjm2], vxy[cjm1], vxy[c], vxy[cjp1]};
+    const double zwd[4] = {by[cim2], by[cim1], by[c], by[cip1]};
+    const double zsd[4] = {bx[cjm2], bx[cjm1], bx[c], bx[cjp1]};
     yv[3] = r[0];
     yb[3] = (R)d[0];
     xv[3] = r[1];
     xb[3] = (R)d[1];
     // E_x: (A, B) = (y, z); a-faces are y-faces, b-faces z-faces
+    R ex, ey, ez;
     {
       const R wv[4] = {r[6], r[7], r[8], r[9]};
       const R wb[4] = {(R)d[2], (R)d[3], (R)d[4], (R)d[5]};
-      ew[c] = emf_from<LIM, EM, R>(yc[0], yc[1], zjm, zc0, wv, wb, yv, yb);
+      ex = emf_from<LIM, EM, R>(yc[0], yc[1], zjm, zc0, wv, wb, yv, yb);
     }
     // E_y: (A, B) = (z, x); a-faces are z-faces, b-faces x-faces
     {
       const R sv[4] = {r[10], r[11], r[12], r[13]};
       const R sb[4] = {(R)d[6], (R)d[7], (R)d[4], (R)d[8]};
-      ew[n + c] = emf_from<LIM, EM, R>(zim, zc0, xc[0], xc[1], xv, xb, sv, sb);
+      ey = emf_from<LIM, EM, R>(zim, zc0, xc[0], xc[1], xv, xb, sv, sb);
     }
-    ew[2 * n + c] = emf_comp<2, LIM, R, EM>(U, FW, g, i, j, k, c);
+    // E_z: a-faces are x-faces, b-faces y-faces
+    {
+      const R wb[4] = {(R)zwd[0], (R)zwd[1], (R)zwd[2], (R)zwd[3]};
+      const R sb[4] = {(R)zsd[0], (R)zsd[1], (R)zsd[2], (R)zsd[3]};
+      ez = emf_from<LIM, EM, R>(xjm, xc[1], yim, yc[1], zwv, wb, zsv, sb);
+    }
+    ew[c] = ex;
+    ew[n + c] = ey;
+    ew[2 * n + c] = ez;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       yv[s] = yv[s + 1];
