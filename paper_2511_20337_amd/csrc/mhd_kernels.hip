@@ -260,10 +260,9 @@ __device__ __forceinline__ R emf_from(const FaceCoef<EM, R>& am, const FaceCoef<
 }
 
 template <int LIM, class R, int EM>
-__global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restrict__ U,
-                                                      const double* __restrict__ FW,
-                                                      double* __restrict__ EW, Geom g,
-                                                      MarchGrid mg) {
+__device__ __forceinline__ void emf_march(const double* __restrict__ U,
+                                          const double* __restrict__ FW, double* __restrict__ EW,
+                                          Geom g, MarchGrid mg) {
   // mixed mode: the XCD-grouped order (0.523 -> 0.513 ms at 256^3; FP64 unchanged)
   const unsigned b = (sizeof(R) == 4) ? xcd_grouped(blockIdx.x, gridDim.x) : blockIdx.x;
   const int tx = (int)(b % (unsigned)mg.ntx);
@@ -335,6 +334,9 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
     const R zsv[4] = {vxy[cjm2], vxy[cjm1], vxy[c], vxy[cjp1]};
     const double zwd[4] = {by[cim2], by[cim1], by[c], by[cip1]};
     const double zsd[4] = {bx[cjm2], bx[cjm1], bx[c], bx[cjp1]};
+    // keep the scheduler from sinking loads into the arithmetic (the minmod
+    // FP64 instantiation otherwise waited for its loads one or two at a time)
+    __builtin_amdgcn_sched_barrier(0);
     yv[3] = r[0];
     yb[3] = (R)d[0];
     xv[3] = r[1];
@@ -371,6 +373,22 @@ __global__ __launch_bounds__(EmfCol::NT) void k_emf_march(const double* __restri
     yc[0] = yc[1];
     xc[0] = xc[1];
   }
+}
+
+// The upwind (EM 0) kernel is held to two waves per SIMD, where it keeps all
+// its loads of a plane in flight without spilling; the UCT-HLLD kernel (EM 1)
+// needs more registers and runs at one.
+template <int LIM, class R>
+__global__ __launch_bounds__(EmfCol::NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_emf_march(const double* __restrict__ U, const double* __restrict__ FW,
+                 double* __restrict__ EW, Geom g, MarchGrid mg) {
+  emf_march<LIM, R, 0>(U, FW, EW, g, mg);
+}
+template <int LIM, class R>
+__global__ __launch_bounds__(EmfCol::NT)
+void k_emf_march_hlld(const double* __restrict__ U, const double* __restrict__ FW,
+                      double* __restrict__ EW, Geom g, MarchGrid mg) {
+  emf_march<LIM, R, 1>(U, FW, EW, g, mg);
 }
 
 template <int DIM, int LIM, class R, int EM>
@@ -1348,9 +1366,14 @@ hipError_t stage_impl(const StageArgs& a) {
     eg.lz = a.g.nz < kMarchRun ? a.g.nz : kMarchRun;
     eg.nzc = (a.g.nz + eg.lz - 1) / eg.lz;
     eg.nblocks = (unsigned)eg.ntx * (unsigned)eg.nty * (unsigned)eg.nzc;
-    MHD_TIMED(a, K_EMF,
-              hipLaunchKernelGGL((k_emf_march<ELIM, R, EM>), dim3(eg.nblocks), dim3(EmfCol::NT), 0,
-                                 a.stream, a.U, a.FW, a.EW, a.g, eg));
+    if constexpr (EM == 1)
+      MHD_TIMED(a, K_EMF,
+                hipLaunchKernelGGL((k_emf_march_hlld<ELIM, R>), dim3(eg.nblocks),
+                                   dim3(EmfCol::NT), 0, a.stream, a.U, a.FW, a.EW, a.g, eg));
+    else
+      MHD_TIMED(a, K_EMF,
+                hipLaunchKernelGGL((k_emf_march<ELIM, R>), dim3(eg.nblocks), dim3(EmfCol::NT), 0,
+                                   a.stream, a.U, a.FW, a.EW, a.g, eg));
   } else {
     MHD_TIMED(a, K_EMF,
               hipLaunchKernelGGL((k_emf<DIM, ELIM, R, EM>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
