@@ -413,6 +413,7 @@ struct Bufs {
   double* BC;    // 3 x n: cell-centred field cotangent
   double* T;     // 8 x n: J^T G of the cell-averaged fields
   double* A;     // 8 x n: cotangent of the stage-1 state
+  double* PW;    // 8 x n: FP64 primitives of the state the stage adjoint linearises at
   double* FWn;   // dim x NSLOT x n: face records at U_n (kept from the stage-1 forward)
   double* EWn;   // 3 x n: edge EMFs at U_n
   // SSP-RK3 only (nullptr otherwise):
@@ -547,6 +548,47 @@ __device__ __forceinline__ void edge_to_face(const double* __restrict__ U,
   bbar += plm_adjoint<LIM>(xb, bp, bm);
 }
 
+// Reconstructed face-frame states of the lower D-face of cell (i,j,k) as
+// face_inputs forms them, from the recovered primitives PW of the four cells
+// c-2..c+1 along D (the values primitive recovery gives, computed once per
+// cell by k_adj_prim), and the staggered normal field.
+template <int DIM, int D, int LIM>
+__device__ __forceinline__ void face_inputs_pw(const double* __restrict__ PW,
+                                               const double* __restrict__ U, const Geom& g,
+                                               int i, int j, int k, double* wl, double* wr,
+                                               double& bn) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  constexpr int slot[7] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4};
+  const int64_t n = g.n;
+  int64_t cs[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) cs[s] = shifted<D>(g, i, j, k, s - 2);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const double* v = PW + (int64_t)slot[q] * n;
+    const double a = v[cs[0]], b = v[cs[1]], c = v[cs[2]], e = v[cs[3]];
+    wl[q] = fma_r(0.5, plm_slope<LIM, double>(b - a, c - b), b);
+    wr[q] = fma_r(-0.5, plm_slope<LIM, double>(c - b, e - c), c);
+  }
+  bn = U[(F_BX + D) * n + cs[2]];
+}
+
+// FP64 primitives of every cell of the stage's state, once, for the face and
+// cell kernels of the stage adjoint (which read each cell's from up to
+// thirteen stencils).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_adj_prim(const double* __restrict__ U,
+                                                     double* __restrict__ PW, Geom g) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= g.n) return;
+  int i, j, k;
+  coords(g, c, i, j, k);
+  double V[8];
+  prim_at<DIM>(U, g, i, j, k, V);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) PW[q * g.n + c] = V[q];
+}
+
 template <int DIM, int D, int LIM, int RS>
 __device__ __forceinline__ void face_adjoint(const double* __restrict__ U,
                                              const double* __restrict__ FW,
@@ -578,7 +620,7 @@ __device__ __forceinline__ void face_adjoint(const double* __restrict__ U,
   if (DIM == 3 || C2 == 2) edge_to_face<C2, 1, LIM>(U, FW, EB, g, i, j, k, c, apbar, ambar, v2bar, bbar);
   // Riemann vector-Jacobian product: one reverse sweep
   double wl[7], wr[7], bn;
-  face_inputs<DIM, D, LIM>(U, g, i, j, k, wl, wr, bn);
+  face_inputs_pw<DIM, D, LIM>(bf.PW, U, g, i, j, k, wl, wr, bn);
   double* wb = bf.WB + (int64_t)D * 14 * n + c;
   double wlb[7], wrb[7], bnbar;
   riemann_vjp<RS>(g.gamma, wl, wr, bn, fb, apbar, ambar, v1bar, v2bar, wlb, wrb, bnbar);
@@ -606,19 +648,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_faces(const double* __restrict__
 
 // ---------------------------------------------------------------------------
 template <int DIM, int D, int LIM>
-__device__ __forceinline__ void plm_cell_adjoint(const double* __restrict__ U,
+__device__ __forceinline__ void plm_cell_adjoint(const double* __restrict__ PW,
                                                  const double* __restrict__ WB, const Geom& g,
                                                  int i, int j, int k, double* vbar) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   constexpr int slot[7] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4};
   const int64_t n = g.n;
+  int64_t cs[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) cs[s] = shifted<D>(g, i, j, k, s - 2);
   double V[5][8];
 #pragma unroll
-  for (int s = 0; s < 5; ++s) {
-    const int o = s - 2;
-    prim_at<DIM>(U, g, D == 0 ? wrap(i + o, g.nx) : i, D == 1 ? wrap(j + o, g.ny) : j,
-                 D == 2 ? wrap(k + o, g.nz) : k, V[s]);
-  }
+  for (int s = 0; s < 5; ++s)
+#pragma unroll
+    for (int q = 0; q < 7; ++q) V[s][slot[q]] = PW[(int64_t)slot[q] * n + cs[s]];
   // faces p (lower face of cell p) for p = c-1 .. c+2 along D
   int64_t fidx[4];
 #pragma unroll
@@ -646,12 +689,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_cells(const double* __restrict__
   coords(g, c, i, j, k);
   const int64_t n = g.n;
   double vb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  plm_cell_adjoint<DIM, 0, LIM>(U, bf.WB, g, i, j, k, vb);
-  plm_cell_adjoint<DIM, 1, LIM>(U, bf.WB, g, i, j, k, vb);
-  if (DIM == 3) plm_cell_adjoint<DIM, 2, LIM>(U, bf.WB, g, i, j, k, vb);
+  plm_cell_adjoint<DIM, 0, LIM>(bf.PW, bf.WB, g, i, j, k, vb);
+  plm_cell_adjoint<DIM, 1, LIM>(bf.PW, bf.WB, g, i, j, k, vb);
+  if (DIM == 3) plm_cell_adjoint<DIM, 2, LIM>(bf.PW, bf.WB, g, i, j, k, vb);
   // primitive recovery: v = m/rho, p = (gamma-1)(E - |m|^2/(2 rho) - |Bc|^2/2)
   double V[8];
-  prim_at<DIM>(U, g, i, j, k, V);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) V[q] = bf.PW[q * n + c];
   const double gm1 = g.gamma - 1.0;
   const double pb = vb[4] * gm1;
   const double irho = 1.0 / V[0];
@@ -779,6 +823,7 @@ Bufs carve(double* scratch, int dim, int64_t n, int integrator) {
   b.BC = p; p += 3 * n;
   b.T = p; p += 8 * n;
   b.A = p; p += 8 * n;
+  b.PW = p; p += 8 * n;
   b.FWn = p; p += (int64_t)dim * NSLOT * n;
   b.EWn = p; p += 3 * n;
   b.FW1 = b.EW1 = b.A1 = nullptr;
@@ -798,6 +843,7 @@ hipError_t stage_adjoint(const AdjointArgs& a, const Bufs& bf, const double* U, 
                          const double* EW, const double* G, double s, const double* Dir,
                          double cd, double* out, double* part) {
   const unsigned nb = blocks_for(a.g.n);
+  hipLaunchKernelGGL((k_adj_prim<DIM>), dim3(nb), dim3(kBlock), 0, a.stream, U, bf.PW, a.g);
   hipLaunchKernelGGL((k_adj_edges<DIM, LIM>), dim3(nb), dim3(kBlock), 0, a.stream, U, FW, G, s,
                      a.g, bf.EB);
   hipLaunchKernelGGL((k_adj_faces<DIM, LIM, RS>), dim3(nb), dim3(kBlock), 0, a.stream, U, FW, G,
@@ -932,7 +978,7 @@ hipError_t adjoint_dim(const AdjointArgs& a) {
 
 size_t adjoint_workspace_bytes(int dim, size_t ncell, int integrator) {
   const size_t nb = (ncell + kBlock - 1) / kBlock;
-  size_t per_cell = 3 * NE + 3 * 14 + 3 + 3 + 8 + 8 + (size_t)dim * NSLOT + 3;
+  size_t per_cell = 3 * NE + 3 * 14 + 3 + 3 + 8 + 8 + 8 + (size_t)dim * NSLOT + 3;
   if (integrator == 1) per_cell += (size_t)dim * NSLOT + 3 + 8;  // FW1, EW1, A1
   return sizeof(double) * (per_cell * ncell + (integrator == 1 ? 3 : 2) * nb) + 256;
 }
