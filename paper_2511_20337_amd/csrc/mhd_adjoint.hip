@@ -499,13 +499,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_edges(const double* __restrict__
 // Cotangents a face receives from the edges of component C that use it.
 // ROLE 0: the face is an a-face of C (normal A = D), its v_B (slot V1) and
 // b_D are reconstructed along B; ROLE 1: a b-face (normal B = D), its v_A
-// (slot V2) and b_D along A.
-template <int C, int ROLE, int LIM>
-__device__ __forceinline__ void edge_to_face(const double* __restrict__ U,
-                                             const double* __restrict__ FW,
-                                             const double* __restrict__ EB, const Geom& g, int i,
-                                             int j, int k, int64_t c, double& apbar,
-                                             double& ambar, double& vbar, double& bbar) {
+// (slot V2) and b_D along A. Split into the loads (edge_load) and the
+// arithmetic (edge_apply), so that a face's loads all go out before any of
+// its arithmetic waits for one.
+struct EdgeIn {
+  double apm, ap0, app, amm, am0, amp;  // alpha+- of the faces c-e, c, c+e
+  double ea0, eap, em0, emp;            // alpha cotangents of the edges at c, c+e
+  double xv[5], xb[5];                  // v and b on the faces c-2e .. c+2e
+  double vp[3], vm[3], bp[3], bm[3];    // cotangents of their edge values
+};
+
+template <int C, int ROLE>
+__device__ __forceinline__ void edge_load(const double* __restrict__ U,
+                                          const double* __restrict__ FW,
+                                          const double* __restrict__ EB, const Geom& g, int i,
+                                          int j, int k, int64_t c, EdgeIn& in) {
   constexpr int A = (C + 1) % 3, B = (C + 2) % 3;
   constexpr int D = ROLE == 0 ? A : B;      // this face's normal
   constexpr int E = ROLE == 0 ? B : A;      // reconstruction / neighbour direction
@@ -517,46 +525,54 @@ __device__ __forceinline__ void edge_to_face(const double* __restrict__ U,
   const double* e = EB + (int64_t)C * NE * n;
   const int64_t cm1 = shifted<E>(g, i, j, k, -1), cp1 = shifted<E>(g, i, j, k, 1);
   const int64_t cm2 = shifted<E>(g, i, j, k, -2), cp2 = shifted<E>(g, i, j, k, 2);
-  // Every value is loaded before any comparison, so that the loads go out
-  // together instead of one round trip per taken branch; the empty asm keeps
-  // the compiler from sinking the four alpha cotangent loads back into the
-  // branches that add them.
   const double* ap = f + S_AP * n;
   const double* am = f + S_AM * n;
-  const double apm = ap[cm1], ap0 = ap[c], app = ap[cp1];
-  const double amm = am[cm1], am0 = am[c], amp = am[cp1];
-  double ea0 = e[sap * n + c], eap = e[sap * n + cp1];
-  double em0 = e[sam * n + c], emp = e[sam * n + cp1];
+  in.apm = ap[cm1]; in.ap0 = ap[c]; in.app = ap[cp1];
+  in.amm = am[cm1]; in.am0 = am[c]; in.amp = am[cp1];
+  in.ea0 = e[sap * n + c]; in.eap = e[sap * n + cp1];
+  in.em0 = e[sam * n + c]; in.emp = e[sam * n + cp1];
   const double* v = f + (ROLE == 0 ? S_V1 : S_V2) * n;
   const double* b = U + (F_BX + D) * n;
-  const double xv[5] = {v[cm2], v[cm1], v[c], v[cp1], v[cp2]};
-  const double xb[5] = {b[cm2], b[cm1], b[c], b[cp1], b[cp2]};
-  const double vp[3] = {e[svlo * n + c], e[svlo * n + cp1], e[svlo * n + cp2]};
-  const double vm[3] = {e[svhi * n + cm1], e[svhi * n + c], e[svhi * n + cp1]};
-  const double bp[3] = {e[sblo * n + c], e[sblo * n + cp1], e[sblo * n + cp2]};
-  const double bm[3] = {e[sbhi * n + cm1], e[sbhi * n + c], e[sbhi * n + cp1]};
-  asm volatile("" : "+v"(ea0), "+v"(eap), "+v"(em0), "+v"(emp));
+  const int64_t c5[5] = {cm2, cm1, c, cp1, cp2};
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    in.xv[s] = v[c5[s]];
+    in.xb[s] = b[c5[s]];
+  }
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    in.vp[s] = e[svlo * n + c5[s + 2]];
+    in.vm[s] = e[svhi * n + c5[s + 1]];
+    in.bp[s] = e[sblo * n + c5[s + 2]];
+    in.bm[s] = e[sbhi * n + c5[s + 1]];
+  }
+}
+
+template <int LIM>
+__device__ __forceinline__ void edge_apply(EdgeIn& in, double& apbar, double& ambar,
+                                           double& vbar, double& bbar) {
+  // the empty asm keeps the compiler from sinking the four alpha cotangent
+  // loads into the branches that add them (one round trip each)
+  asm volatile("" : "+v"(in.ea0), "+v"(in.eap), "+v"(in.em0), "+v"(in.emp));
   // alpha: the edge at c takes max(face c-e, face c); the edge at c+e takes
   // max(face c, face c+e); the first argument wins ties.
-  apbar = (ap0 > apm) ? apbar + ea0 : apbar;
-  apbar = !(app > ap0) ? apbar + eap : apbar;
-  ambar = (am0 > amm) ? ambar + em0 : ambar;
-  ambar = !(amp > am0) ? ambar + emp : ambar;
+  apbar = (in.ap0 > in.apm) ? apbar + in.ea0 : apbar;
+  apbar = !(in.app > in.ap0) ? apbar + in.eap : apbar;
+  ambar = (in.am0 > in.amm) ? ambar + in.em0 : ambar;
+  ambar = !(in.amp > in.am0) ? ambar + in.emp : ambar;
   // reconstructed values: upper extrapolation of face p feeds the edge at
   // p+e (as its lower value), the lower extrapolation feeds the edge at p
-  vbar += plm_adjoint<LIM>(xv, vp, vm);
-  bbar += plm_adjoint<LIM>(xb, bp, bm);
+  vbar += plm_adjoint<LIM>(in.xv, in.vp, in.vm);
+  bbar += plm_adjoint<LIM>(in.xb, in.bp, in.bm);
 }
 
 // Reconstructed face-frame states of the lower D-face of cell (i,j,k) as
 // face_inputs forms them, from the recovered primitives PW of the four cells
 // c-2..c+1 along D (the values primitive recovery gives, computed once per
-// cell by k_adj_prim), and the staggered normal field.
-template <int DIM, int D, int LIM>
-__device__ __forceinline__ void face_inputs_pw(const double* __restrict__ PW,
-                                               const double* __restrict__ U, const Geom& g,
-                                               int i, int j, int k, double* wl, double* wr,
-                                               double& bn) {
+// cell by k_adj_prim): pw_load gathers the 28 values, pw_states reconstructs.
+template <int D>
+__device__ __forceinline__ void pw_load(const double* __restrict__ PW, const Geom& g, int i,
+                                        int j, int k, double (&v)[7][4]) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   constexpr int slot[7] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4};
   const int64_t n = g.n;
@@ -564,13 +580,18 @@ __device__ __forceinline__ void face_inputs_pw(const double* __restrict__ PW,
 #pragma unroll
   for (int s = 0; s < 4; ++s) cs[s] = shifted<D>(g, i, j, k, s - 2);
 #pragma unroll
+  for (int q = 0; q < 7; ++q)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[q][s] = PW[(int64_t)slot[q] * n + cs[s]];
+}
+template <int LIM>
+__device__ __forceinline__ void pw_states(const double (&v)[7][4], double* wl, double* wr) {
+#pragma unroll
   for (int q = 0; q < 7; ++q) {
-    const double* v = PW + (int64_t)slot[q] * n;
-    const double a = v[cs[0]], b = v[cs[1]], c = v[cs[2]], e = v[cs[3]];
+    const double a = v[q][0], b = v[q][1], c = v[q][2], e = v[q][3];
     wl[q] = fma_r(0.5, plm_slope<LIM, double>(b - a, c - b), b);
     wr[q] = fma_r(-0.5, plm_slope<LIM, double>(c - b, e - c), c);
   }
-  bn = U[(F_BX + D) * n + cs[2]];
 }
 
 // FP64 primitives of every cell of the stage's state, once, for the face and
@@ -596,31 +617,48 @@ __device__ __forceinline__ void face_adjoint(const double* __restrict__ U,
                                              const double* __restrict__ EB, const Geom& g, int i,
                                              int j, int k, int64_t c, const Bufs& bf) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  constexpr int C1 = (D + 2) % 3;  // this face is an a-face of C1
+  constexpr int C2 = (D + 1) % 3;  // and a b-face of C2
+  constexpr bool E1 = (DIM == 3 || C1 == 2), E2 = (DIM == 3 || C2 == 2);
   const int64_t n = g.n;
   const int64_t cm = shifted<D>(g, i, j, k, -1);
   const double idl = s / delta<D>(g);
+  // Gather: every value the face needs, issued before any of it is used.
+  constexpr int NG = (DIM == 2) ? 6 : 5;
+  constexpr int gq[6] = {0, F_MX + D, F_MX + T1, F_MX + T2, F_EN, F_BZ};
+  double gc[NG], gm[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    gc[q] = G[gq[q] * n + c];
+    gm[q] = G[gq[q] * n + cm];
+  }
+  EdgeIn e1, e2;
+  if (E1) edge_load<C1, 0>(U, FW, EB, g, i, j, k, c, e1);
+  if (E2) edge_load<C2, 1>(U, FW, EB, g, i, j, k, c, e2);
+  double pv[7][4];
+  pw_load<D>(bf.PW, g, i, j, k, pv);
+  const double bn = U[(F_BX + D) * n + c];
+  __builtin_amdgcn_sched_barrier(0);
   // flux cotangents (face frame: rho, m_n, m_t1, m_t2, B_t1, B_t2, E)
   double fb[7];
-  fb[0] = (G[c] - G[cm]) * idl;
-  fb[1] = (G[(F_MX + D) * n + c] - G[(F_MX + D) * n + cm]) * idl;
-  fb[2] = (G[(F_MX + T1) * n + c] - G[(F_MX + T1) * n + cm]) * idl;
-  fb[3] = (G[(F_MX + T2) * n + c] - G[(F_MX + T2) * n + cm]) * idl;
+  fb[0] = (gc[0] - gm[0]) * idl;
+  fb[1] = (gc[1] - gm[1]) * idl;
+  fb[2] = (gc[2] - gm[2]) * idl;
+  fb[3] = (gc[3] - gm[3]) * idl;
   fb[4] = 0.0;
   fb[5] = 0.0;
-  fb[6] = (G[F_EN * n + c] - G[F_EN * n + cm]) * idl;
+  fb[6] = (gc[4] - gm[4]) * idl;
   if (DIM == 2) {
-    const double bz = (G[F_BZ * n + c] - G[F_BZ * n + cm]) * idl;
+    const double bz = (gc[NG - 1] - gm[NG - 1]) * idl;
     if (D == 0) fb[5] = bz; else fb[4] = bz;   // B_z is t2 of x-faces, t1 of y-faces
   }
   // cotangents from the edges
   double apbar = 0.0, ambar = 0.0, v1bar = 0.0, v2bar = 0.0, bbar = 0.0;
-  constexpr int C1 = (D + 2) % 3;  // this face is an a-face of C1
-  constexpr int C2 = (D + 1) % 3;  // and a b-face of C2
-  if (DIM == 3 || C1 == 2) edge_to_face<C1, 0, LIM>(U, FW, EB, g, i, j, k, c, apbar, ambar, v1bar, bbar);
-  if (DIM == 3 || C2 == 2) edge_to_face<C2, 1, LIM>(U, FW, EB, g, i, j, k, c, apbar, ambar, v2bar, bbar);
+  if (E1) edge_apply<LIM>(e1, apbar, ambar, v1bar, bbar);
+  if (E2) edge_apply<LIM>(e2, apbar, ambar, v2bar, bbar);
   // Riemann vector-Jacobian product: one reverse sweep
-  double wl[7], wr[7], bn;
-  face_inputs_pw<DIM, D, LIM>(bf.PW, U, g, i, j, k, wl, wr, bn);
+  double wl[7], wr[7];
+  pw_states<LIM>(pv, wl, wr);
   double* wb = bf.WB + (int64_t)D * 14 * n + c;
   double wlb[7], wrb[7], bnbar;
   riemann_vjp<RS>(g.gamma, wl, wr, bn, fb, apbar, ambar, v1bar, v2bar, wlb, wrb, bnbar);
