@@ -55,11 +55,11 @@ FACE_BYTES = 64
 FP32_PEAK = 157.3e12
 # HBM bytes per cell of one face-kernel launch, rocprofv3 FETCH_SIZE x 2.0 and
 # WRITE_SIZE x 1.0 (the copy-kernel calibration), for the kernel as it stands.
-FACE_TRAFFIC = {"fp64": 189.1 + 216.0, "mixed": 190.0 + 108.0}
+FACE_TRAFFIC = {"fp64": 189.0 + 216.0, "mixed": 190.0 + 108.0}
 # HBM bytes per cell of one whole step, the same counters summed over its
 # launches (two of faces and EMF, the updates of both stages): what the
 # three-kernel stage moves beside the 320 algorithmic bytes.
-STEP_TRAFFIC = {"fp64": 1983.9, "mixed": 1321.6}
+STEP_TRAFFIC = {"fp64": 1988.2, "mixed": 1322.6}
 # WENO-Z face kernel on the 3D Orszag-Tang problem (FP64, HLLD): algorithmic
 # flops per cell of the oracle's face phase on that workload at 256^3 (count_flops.py;
 # its textbook WENO-Z with seven divisions per value, each one flop), and the
