@@ -1295,7 +1295,6 @@ hipError_t glm_stage_lim(const StageArgs& a) {
   return mixed ? glm_stage_impl<DIM, 1, 1, float>(a) : glm_stage_impl<DIM, 1, 1, double>(a);
 }
 
-unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <class T>
 TileGrid tile_grid(const Geom& g) {
