@@ -665,18 +665,21 @@ __device__ __forceinline__ void weno_face(const double* __restrict__ PW,
     cs[s] = lin(g, D == 0 ? wrap_any(i + o, g.nx) : i, D == 1 ? wrap_any(j + o, g.ny) : j,
                 D == 2 ? wrap_any(k + o, g.nz) : k);
   }
+  double v[7][6];
+#pragma unroll
+  for (int q = 0; q < 7; ++q)
+#pragma unroll
+    for (int s = 0; s < 6; ++s) v[q][s] = PW[slot[q] * n + cs[s]];
+  const double bn = U[(F_BX + D) * n + c];
+  __builtin_amdgcn_sched_barrier(0);
   double wl[7], wr[7];
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
-    const double* w = PW + slot[q] * n;
-    double v[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) v[s] = w[cs[s]];
-    wl[q] = wenoz_upper(v[0], v[1], v[2], v[3], v[4]);
-    wr[q] = wenoz_upper(v[5], v[4], v[3], v[2], v[1]);
+    wl[q] = wenoz_upper(v[q][0], v[q][1], v[q][2], v[q][3], v[q][4]);
+    wr[q] = wenoz_upper(v[q][5], v[q][4], v[q][3], v[q][2], v[q][1]);
   }
   RiemannOut<double> o;
-  riemann<RS, double, EM>(g.gamma, wl, wr, U[(F_BX + D) * n + c], o);
+  riemann<RS, double, EM>(g.gamma, wl, wr, bn, o);
   put_record<DIM, D, EM, double>(FW, n, c, o);
 }
 
