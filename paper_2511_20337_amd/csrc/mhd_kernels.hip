@@ -1163,20 +1163,25 @@ __device__ __forceinline__ void glm_face(const double* __restrict__ PW, double* 
     cs[s] = lin(g, D == 0 ? wrap_any(i + o, g.nx) : i, D == 1 ? wrap_any(j + o, g.ny) : j,
                 D == 2 ? wrap_any(k + o, g.nz) : k);
   }
+  // the stencil's 9 x NS primitives are all loaded before a scheduling
+  // barrier (one wait per face instead of one per quantity)
+  double pv[9][NS];
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) pv[q][s] = PW[slot[q] * n + cs[s]];
+  __builtin_amdgcn_sched_barrier(0);
   R wl[9], wr[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const double* w = PW + slot[q] * n;
+    const double* v8 = pv[q];
     if constexpr (LIM == 2) {
-      double v[6];
-#pragma unroll
-      for (int s = 0; s < 6; ++s) v[s] = w[cs[s]];
-      wl[q] = (R)wenoz_upper(v[0], v[1], v[2], v[3], v[4]);
-      wr[q] = (R)wenoz_upper(v[5], v[4], v[3], v[2], v[1]);
+      wl[q] = (R)wenoz_upper(v8[0], v8[1], v8[2], v8[3], v8[4]);
+      wr[q] = (R)wenoz_upper(v8[5], v8[4], v8[3], v8[2], v8[1]);
     } else {
       R v[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) v[s] = (R)w[cs[s]];
+      for (int s = 0; s < 4; ++s) v[s] = (R)v8[s];
       wl[q] = fma_r(R(0.5), plm_slope<LIM, R>(v[1] - v[0], v[2] - v[1]), v[1]);
       wr[q] = fma_r(R(-0.5), plm_slope<LIM, R>(v[2] - v[1], v[3] - v[2]), v[2]);
     }
