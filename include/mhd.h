@@ -93,7 +93,8 @@ typedef enum { MHD_DIVB_CT = 0, MHD_DIVB_GLM = 1 } mhd_divb;
 
 typedef struct {
   int32_t dim;                  /* 2 or 3 */
-  int32_t nx, ny, nz;           /* cells per direction; nz == 1 when dim == 2; each >= 4 otherwise */
+  int32_t nx, ny, nz;           /* cells per direction; nz == 1 when dim == 2; each >= 4 otherwise;
+                                   at most 4e9 cells, and in 3D fewer than 2^29 per x-y plane */
   double xmin, xmax, ymin, ymax, zmin, zmax;  /* periodic box (max > min) */
   double gamma;                 /* adiabatic index, > 1 */
   double cfl;                   /* Courant number C > 0: dt = C min_d,cells dx_d/(|v_d|+c_f,d) */

@@ -128,6 +128,9 @@ bool cfg_valid(const mhd_config* c) {
   // 64-bit cell count; per-axis sizes bounded so index arithmetic stays in int
   const double cells = (double)c->nx * c->ny * c->nz;
   if (cells > 4.0e9) return false;
+  // the 3D z-marching kernels address a plane of one field with 32-bit byte
+  // offsets: fewer than 2^29 cells per plane
+  if (c->dim == 3 && (double)c->nx * c->ny >= 536870912.0) return false;
   return true;
 }
 

@@ -55,6 +55,17 @@ def test_init_validates_config():
     with pytest.raises(mhd.MHDError) as e:
         mhd.mhd_init(mhd.config_from(dict(s, divb="glm", emf="uct_hlld")))
     assert e.value.status == mhd.MHD_ERR_INVALID
+    # a 3D plane of 2^29 cells or more (the march kernels' 32-bit in-plane
+    # byte offsets), and more than 4e9 cells in all
+    for nx, ny, nz in ((32768, 16384, 4), (2048, 2048, 1024)):
+        cfg = mhd.config_from(s)
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        with pytest.raises(mhd.MHDError) as e:
+            mhd.mhd_init(cfg)
+        assert e.value.status == mhd.MHD_ERR_INVALID, (nx, ny, nz)
+    cfg = mhd.config_from(s)
+    cfg.nx, cfg.ny, cfg.nz = 16384, 16384, 4  # 2^28 cells per plane: accepted
+    mhd.mhd_destroy(mhd.mhd_init(cfg))
     s2, _ = W.orszag_tang_2d(8)
     cfg = mhd.config_from(s2)
     cfg.nz = 4  # 2D needs nz == 1
