@@ -153,6 +153,14 @@ def _time_backward(AD, ctx, U0, dts, every):
     return n / (t2 - t1), n / (t1 - t0)
 
 
+# The largest cube on which the blast's checkpointed 16-step adjoint fits in one
+# MI355X's 288 GB: the library's forward and adjoint workspaces (188 doubles per
+# cell with SSP-RK2) plus the state, four checkpoints, the replayed segment and
+# the two cotangents (about 96 more) make 284 doubles per cell, 204 GB at 448^3
+# (305 GB at 512^3; the 640^3 of the blast configuration would need 596 GB).
+ADJ_LARGE_N = 448
+
+
 def time_adjoint_blast(n, nsteps, every, integrator="rk2"):
     """Magnetised blast n^3 in FP64: N forward steps with checkpoints, then the
     checkpointed backward. Returns adjoint steps/s and forward steps/s."""
@@ -278,6 +286,10 @@ def only_part(part, n, steps, warmup):
         adj, fwd = time_adjoint(512, 64, 8)
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
                "workload": "kelvin_helmholtz_2d_512"}
+    elif part == "adjoint_3d_large":
+        adj, fwd = time_adjoint_blast(ADJ_LARGE_N, 16, 4)
+        out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
+               "workload": "blast_3d_%d_fp64 ssp_rk2" % ADJ_LARGE_N}
     else:
         integ = "rk3" if part == "adjoint_3d_rk3" else "rk2"
         adj, fwd = time_adjoint_blast(256, 16, 4, integ)
@@ -302,7 +314,8 @@ def main(argv=None):
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters) and exit")
     ap.add_argument("--only", choices=("mixed", "ot3d_wenoz", "glm", "ot2d_graph", "adjoint",
-                                       "adjoint_3d", "adjoint_3d_rk3"), default=None,
+                                       "adjoint_3d", "adjoint_3d_rk3", "adjoint_3d_large"),
+                    default=None,
                     help="run only this extra measurement and print it (for profiling)")
     args = ap.parse_args(argv)
     if args.copy_probe:
@@ -445,6 +458,13 @@ def main(argv=None):
         adj3r, fwd3r = time_adjoint_blast(256, 16, 4, "rk3")
         out["adjoint_3d"]["rk3"] = {"value": adj3r, "unit": "adjoint steps/s",
                                     "forward_steps_per_s": fwd3r}
+        log("adjoint: blast %d^3 FP64, the largest cube whose adjoint fits in HBM" % ADJ_LARGE_N)
+        import torch
+        torch.cuda.empty_cache()
+        adjl, fwdl = time_adjoint_blast(ADJ_LARGE_N, 16, 4)
+        out["adjoint_3d"]["large"] = {"value": adjl, "unit": "adjoint steps/s",
+                                      "forward_steps_per_s": fwdl,
+                                      "workload": "blast_3d_%d_fp64" % ADJ_LARGE_N}
     if not args.no_cpu:
         log("cpu baseline: oracle at %d^3" % args.cpu_n)
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, make, args.cpu_steps)
