@@ -511,9 +511,9 @@ __device__ __forceinline__ void pslot_pos(int e, int& x, int& y, int& z) {
 
 // One lower face of direction D of the tile cell (x,y,z) from LDS primitives.
 template <int DIM, int D, int LIM, int RS, class R, int EM>
-__device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM],
-                                          const double* __restrict__ U, double* __restrict__ FW,
-                                          const Geom& g, int x, int y, int z, int64_t c) {
+__device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM], R bn,
+                                          double* __restrict__ FW, const Geom& g, int x, int y,
+                                          int z, int64_t c) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   constexpr int slot[7] = {0, 1 + D, 1 + T1, 1 + T2, 5 + T1, 5 + T2, 4};
   int e[4];
@@ -530,7 +530,6 @@ __device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM],
     wl[q] = fma_r(R(0.5), plm_slope<LIM, R>(b - a, cc - b), b);
     wr[q] = fma_r(R(-0.5), plm_slope<LIM, R>(cc - b, d - cc), cc);
   }
-  const R bn = (R)U[(F_BX + D) * g.n + c];
   RiemannOut<R> o;
   riemann<RS, R, EM>((R)g.gamma, wl, wr, bn, o);
   put_record<DIM, D, EM, R>(FW, g.n, c, o);
@@ -548,6 +547,17 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
   __shared__ R sp[8][T::NPRIM];
   int i0, j0, k0;
   tile_origin<DIM>(tg, blockIdx.x, i0, j0, k0);
+  const int x = threadIdx.x % T::TX, y = (threadIdx.x / T::TX) % T::TY,
+            z = threadIdx.x / (T::TX * T::TY);
+  const int i = i0 + x, j = j0 + y, k = k0 + z;
+  const bool inside = i < g.nx && j < g.ny && k < g.nz;
+  // The normal fields of the cell's faces first (any in-bounds cell for a
+  // thread outside the grid): loaded after the x-face records, waiting for
+  // them would wait for those stores too.
+  const int64_t c = lin(g, min(i, g.nx - 1), min(j, g.ny - 1), min(k, g.nz - 1));
+  R bn[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) bn[d] = (R)U[(F_BX + d) * g.n + c];
   bool bad = false;
   for (int e = threadIdx.x; e < T::NPRIM; e += T::NCORE) {
     int x, y, z;
@@ -560,14 +570,10 @@ __global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* 
   }
   if (bad) atomicOr(flag, 1);
   __syncthreads();
-  const int x = threadIdx.x % T::TX, y = (threadIdx.x / T::TX) % T::TY,
-            z = threadIdx.x / (T::TX * T::TY);
-  const int i = i0 + x, j = j0 + y, k = k0 + z;
-  if (i >= g.nx || j >= g.ny || k >= g.nz) return;
-  const int64_t c = lin(g, i, j, k);
-  tile_face<DIM, 0, LIM, RS, R, EM>(sp, U, FW, g, x, y, z, c);
-  tile_face<DIM, 1, LIM, RS, R, EM>(sp, U, FW, g, x, y, z, c);
-  if (DIM == 3) tile_face<DIM, 2, LIM, RS, R, EM>(sp, U, FW, g, x, y, z, c);
+  if (!inside) return;
+  tile_face<DIM, 0, LIM, RS, R, EM>(sp, bn[0], FW, g, x, y, z, c);
+  tile_face<DIM, 1, LIM, RS, R, EM>(sp, bn[1], FW, g, x, y, z, c);
+  if (DIM == 3) tile_face<DIM, 2, LIM, RS, R, EM>(sp, bn[DIM - 1], FW, g, x, y, z, c);
 }
 
 // ---------------------------------------------------------------------------
