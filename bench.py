@@ -153,6 +153,11 @@ def _time_backward(AD, ctx, U0, dts, every):
     return n / (t2 - t1), n / (t1 - t0)
 
 
+# Checkpoint interval of the adjoint measurements at 512^2 and 256^3: every
+# state of the forward pass is kept (64 x 16.8 MB, 16 x 1.07 GB), so the
+# backward replays nothing; HBM holds them easily next to the workspaces.
+ADJ_EVERY = 1
+
 # The largest cube on which the blast's checkpointed 16-step adjoint fits in one
 # MI355X's 288 GB: the library's forward and adjoint workspaces (188 doubles per
 # cell with SSP-RK2) plus the state, four checkpoints, the replayed segment and
@@ -229,7 +234,9 @@ def cpu_baseline(n_sample: int, setup_fn, steps: int = 2):
 
 
 def copy_probe(mib: int) -> int:
-    """A plain copy of known size, timed, as the reference for HBM counters."""
+    """A plain copy of known size, timed, as the reference for HBM counters;
+    then the practical HBM rates of a copy, a read-only sum and a fill of the
+    same buffers (HIP events over ten calls each, after three untimed)."""
     import torch
     n = mib * (1 << 20) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda:0")
@@ -240,8 +247,22 @@ def copy_probe(mib: int) -> int:
         dst.copy_(src)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / 5
+    rates = {}
+    for name, fn, nbytes in (("copy", lambda: dst.copy_(src), 2 * n * 8),
+                             ("sum", lambda: src.sum(), n * 8),
+                             ("fill", lambda: dst.fill_(1.0), n * 8)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        rates[name] = nbytes / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
-                      "copies": 5, "GBps": 2 * n * 8 / el / 1e9}), flush=True)
+                      "copies": 5, "GBps": 2 * n * 8 / el / 1e9,
+                      "event_GBps": rates}), flush=True)
     return 0
 
 
@@ -283,7 +304,7 @@ def only_part(part, n, steps, warmup):
     elif part == "ot2d_graph":
         out = dict({"part": part}, **time_2d_graph())
     elif part == "adjoint":
-        adj, fwd = time_adjoint(512, 64, 8)
+        adj, fwd = time_adjoint(512, 64, ADJ_EVERY)
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
                "workload": "kelvin_helmholtz_2d_512"}
     elif part == "adjoint_3d_large":
@@ -292,7 +313,7 @@ def only_part(part, n, steps, warmup):
                "workload": "blast_3d_%d_fp64 ssp_rk2" % ADJ_LARGE_N}
     else:
         integ = "rk3" if part == "adjoint_3d_rk3" else "rk2"
-        adj, fwd = time_adjoint_blast(256, 16, 4, integ)
+        adj, fwd = time_adjoint_blast(256, 16, ADJ_EVERY, integ)
         out = {"part": part, "value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
                "workload": "blast_3d_256_fp64 ssp_%s" % integ}
     print(json.dumps(out), flush=True)
@@ -443,19 +464,23 @@ def main(argv=None):
                       "kernels": {k: {"avg_ms": v[0] / v[1]} for k, v in kt_g.items() if v[1]}}
         log("2D Orszag-Tang 128^2: eager steps and steps replayed from a HIP graph")
         out["orszag_tang_2d"] = time_2d_graph()
-        log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, checkpoints every 8")
-        adj, fwd = time_adjoint(512, 64, 8)
+        log("adjoint: Kelvin-Helmholtz 512^2, 64 steps, every state kept")
+        adj, fwd = time_adjoint(512, 64, ADJ_EVERY)
         out["adjoint"] = {"value": adj, "unit": "adjoint steps/s", "forward_steps_per_s": fwd,
                           "config": {"workload": "kelvin_helmholtz_2d_512", "steps": 64,
-                                     "checkpoint_every": 8}}
-        log("adjoint: blast 256^3 FP64, 16 steps, checkpoints every 4")
-        adj3, fwd3 = time_adjoint_blast(256, 16, 4)
+                                     "checkpoint_every": ADJ_EVERY}}
+        log("adjoint: blast 256^3 FP64, 16 steps, every state kept")
+        adj3, fwd3 = time_adjoint_blast(256, 16, ADJ_EVERY)
         out["adjoint_3d"] = {"value": adj3, "unit": "adjoint steps/s",
                              "forward_steps_per_s": fwd3,
                              "config": {"workload": "blast_3d_256_fp64", "steps": 16,
-                                        "checkpoint_every": 4}}
+                                        "checkpoint_every": ADJ_EVERY}}
+        log("adjoint: the same with checkpoints every 4 steps (segments replayed)")
+        adj34, fwd34 = time_adjoint_blast(256, 16, 4)
+        out["adjoint_3d"]["checkpoint_every_4"] = {"value": adj34, "unit": "adjoint steps/s",
+                                                   "forward_steps_per_s": fwd34}
         log("adjoint: the same with SSP-RK3")
-        adj3r, fwd3r = time_adjoint_blast(256, 16, 4, "rk3")
+        adj3r, fwd3r = time_adjoint_blast(256, 16, ADJ_EVERY, "rk3")
         out["adjoint_3d"]["rk3"] = {"value": adj3r, "unit": "adjoint steps/s",
                                     "forward_steps_per_s": fwd3r}
         log("adjoint: blast %d^3 FP64, the largest cube whose adjoint fits in HBM" % ADJ_LARGE_N)
@@ -464,7 +489,8 @@ def main(argv=None):
         adjl, fwdl = time_adjoint_blast(ADJ_LARGE_N, 16, 4)
         out["adjoint_3d"]["large"] = {"value": adjl, "unit": "adjoint steps/s",
                                       "forward_steps_per_s": fwdl,
-                                      "workload": "blast_3d_%d_fp64" % ADJ_LARGE_N}
+                                      "workload": "blast_3d_%d_fp64" % ADJ_LARGE_N,
+                                      "checkpoint_every": 4}
     if not args.no_cpu:
         log("cpu baseline: oracle at %d^3" % args.cpu_n)
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, make, args.cpu_steps)

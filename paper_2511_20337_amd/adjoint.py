@@ -4,7 +4,8 @@ Forward runs N steps of ``mhd_step`` with a given (frozen) time-step sequence
 and keeps a checkpoint of the state every ``every`` steps. Backward replays
 each segment forward from its checkpoint (storing that segment's states) and
 applies ``mhd_adjoint_step`` in reverse. Memory: N/every checkpoints plus one
-segment of ``every`` states. Torch only holds buffers and orders the calls;
+segment of ``every`` states; ``every = 1`` keeps every state of the forward
+pass, so the backward replays nothing. Torch only holds buffers and orders the calls;
 all arithmetic runs in the HIP kernels.
 """
 from __future__ import annotations
@@ -49,7 +50,9 @@ class MHDSteps(torch.autograd.Function):
         for start in reversed(sorted(fctx.checkpoints)):
             stop = min(start + fctx.every, n)
             # replay the segment, keeping the state at the start of each step
-            states = [fctx.checkpoints[start].clone()]
+            # (the adjoint step only reads its state, so the checkpoint itself
+            # serves as the first)
+            states = [fctx.checkpoints[start]]
             for s in range(start, stop - 1):
                 U = states[-1].clone()
                 solver.step(U, dts[s])
