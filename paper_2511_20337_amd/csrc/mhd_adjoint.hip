@@ -97,12 +97,15 @@ __device__ __forceinline__ void cfast_vjp(double g, const double* w, double bn, 
   const double sd = sqrt_r(disc);
   const double q = div_r(a + sd, 2.0 * rho);
   const double cf = sqrt_r(q);
-  const double qb = cf > 0.0 ? cfb * 0.5 / cf : 0.0;
-  const double i2r = 0.5 / rho;
+  // reciprocals from the refined estimate (a few ulps from the quotients);
+  // the selects drop the non-finite values at cf = 0, sd = 0
+  const double qb = cf > 0.0 ? cfb * 0.5 * rcp_r(cf) : 0.0;
+  const double irho = rcp_r(rho);
+  const double i2r = 0.5 * irho;
   double ab = qb * i2r;
   const double sdb = qb * i2r;
-  const double rhob = -qb * q / rho;
-  const double discb = sd > 0.0 ? sdb * 0.5 / sd : 0.0;
+  const double rhob = -qb * q * irho;
+  const double discb = sd > 0.0 ? sdb * 0.5 * rcp_r(sd) : 0.0;
   const double xb = (x > 0.0) ? discb : 0.0;
   ab += 2.0 * a * xb;
   const double gpb = -4.0 * bn2 * xb + ab;
@@ -279,13 +282,14 @@ __device__ __forceinline__ void riemann_vjp(double g, const double* wl, const do
     // Alfven fronts S*_L = S_M - |bn|/sql, S*_R = S_M + |bn|/sqr
     {
       sb.sm += slsb + srsb;
-      const double ql = t.abn / t.sql, qr = t.abn / t.sqr;
-      const double abnb = -slsb / t.sql + srsb / t.sqr;
-      sqlb += slsb * ql / t.sql;
-      sqrb -= srsb * qr / t.sqr;
+      const double isl = rcp_r(t.sql), isr = rcp_r(t.sqr);
+      const double ql = t.abn * isl, qr = t.abn * isr;
+      const double abnb = -slsb * isl + srsb * isr;
+      sqlb += slsb * ql * isl;
+      sqrb -= srsb * qr * isr;
       bnb += abnb * (bn < 0.0 ? -1.0 : 1.0);
-      sb.rs[0] += t.sql > 0.0 ? sqlb * 0.5 / t.sql : 0.0;
-      sb.rs[1] += t.sqr > 0.0 ? sqrb * 0.5 / t.sqr : 0.0;
+      sb.rs[0] += t.sql > 0.0 ? sqlb * 0.5 * isl : 0.0;
+      sb.rs[1] += t.sqr > 0.0 ? sqrb * 0.5 * isr : 0.0;
     }
     // star states of both sides
     double bn2b = 0.0, mlb = 0.0, mrb = 0.0, dlb = 0.0, drb = 0.0;
