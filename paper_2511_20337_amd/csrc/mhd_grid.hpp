@@ -104,17 +104,17 @@ __device__ __forceinline__ void face_inputs(const double* __restrict__ U, const 
 // Partial derivatives (d slope/d dm, d slope/d dp) of the limited slope.
 template <int LIM>
 __device__ __forceinline__ void plm_slope_grad(double dm, double dp, double& s1, double& s2) {
-  if (dm * dp <= 0.0) {
-    s1 = 0.0;
-    s2 = 0.0;
-  } else if (LIM == 0) {
+  const bool ext = dm * dp <= 0.0;
+  if (LIM == 0) {
     const bool left = __builtin_fabs(dm) <= __builtin_fabs(dp);
-    s1 = left ? 1.0 : 0.0;
-    s2 = left ? 0.0 : 1.0;
+    s1 = (ext || !left) ? 0.0 : 1.0;
+    s2 = (ext || left) ? 0.0 : 1.0;
   } else {
-    const double is = 1.0 / (dm + dp);
-    s1 = 2.0 * dp * dp * is * is;
-    s2 = 2.0 * dm * dm * is * is;
+    // branch-free: at extrema (where dm + dp may vanish) the select drops the
+    // value of the refined reciprocal
+    const double is = rcp_r(dm + dp);
+    s1 = ext ? 0.0 : 2.0 * dp * dp * is * is;
+    s2 = ext ? 0.0 : 2.0 * dm * dm * is * is;
   }
 }
 
