@@ -401,8 +401,21 @@ __device__ __forceinline__ void riemann_vjp(double g, const double* wl, const do
   if (wr[1] < wl[1]) wrb[1] += slb; else wlb[1] += slb;
   if (wr[1] > wl[1]) wrb[1] += srb; else wlb[1] += srb;
   const double cmb = srb - slb;
-  if (t.cr > t.cl) cfast_vjp(g, wr, bn, cmb, wrb, bnb);
-  else cfast_vjp(g, wl, bn, cmb, wlb, bnb);
+  {
+    // one evaluation on the side whose fast speed was taken, by selects
+    const bool rs = t.cr > t.cl;
+    double wc[7], wcb[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 7; ++q) wc[q] = rs ? wr[q] : wl[q];
+    cfast_vjp(g, wc, bn, cmb, wcb, bnb);
+    constexpr int touched[4] = {0, 4, 5, 6};  // rho, B_t1, B_t2, p
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int q = touched[e];
+      wrb[q] += rs ? wcb[q] : 0.0;
+      wlb[q] += rs ? 0.0 : wcb[q];
+    }
+  }
   phys_vjp(igm1, wl, bn, ulb, flb, ptlb, wlb, bnb);
   phys_vjp(igm1, wr, bn, urb, frb, ptrb, wrb, bnb);
 }
