@@ -501,7 +501,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_edges(const double* __restrict__
                                                       const double* __restrict__ FW,
                                                       const double* __restrict__ G, double s,
                                                       Geom g, double* __restrict__ EB) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // XCD-grouped workgroup order: the rows above and below, which the stencil
+  // reads, mostly come through the same L2 (KH 512^2 adjoint 2878 -> 3041
+  // steps/s, blast 256^3 30.5 -> 31.1, for edges, faces and cells together)
+  const int64_t c = (int64_t)xcd_grouped(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (c >= g.n) return;
   int i, j, k;
   coords(g, c, i, j, k);
@@ -692,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_faces(const double* __restrict__
                                                       const double* __restrict__ FW,
                                                       const double* __restrict__ G, double s,
                                                       Geom g, Bufs bf) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t c = (int64_t)xcd_grouped(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (c >= g.n) return;
   int i, j, k;
   coords(g, c, i, j, k);
@@ -738,7 +741,7 @@ __device__ __forceinline__ void plm_cell_adjoint(const double* __restrict__ PW,
 template <int DIM, int LIM>
 __global__ __launch_bounds__(kBlock) void k_adj_cells(const double* __restrict__ U, Geom g,
                                                       Bufs bf) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t c = (int64_t)xcd_grouped(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (c >= g.n) return;
   int i, j, k;
   coords(g, c, i, j, k);

@@ -27,6 +27,22 @@ namespace mhd {
 
 enum : int { F_RHO = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_EN = 4, F_BX = 5, F_BY = 6, F_BZ = 7 };
 
+// Workgroup order of the WENO-Z kernels, of the mixed-mode EMF and update
+// kernels and of the adjoint's gather kernels: the hardware deals workgroups
+// round-robin to the 8 XCDs, each with its own L2. Within every full group of
+// 512 workgroups, XCD x is given the 64 consecutive ones x*64 .. x*64+63, so
+// that neighbouring rows (the stencil's reach along y) are mostly read through
+// the same L2, while all XCDs still advance together through the domain and
+// share the Infinity Cache. A permutation of 0 .. nb-1; a last partial group
+// keeps its order. (Measured slower for the z-marching face kernel, whose
+// neighbouring columns share the Infinity Cache better round-robin.)
+__device__ __forceinline__ unsigned xcd_grouped(unsigned b, unsigned nb) {
+  const unsigned grp = b / 512u;
+  if ((grp + 1u) * 512u > nb) return b;
+  const unsigned w = b % 512u;
+  return grp * 512u + (w % 8u) * 64u + w / 8u;
+}
+
 // Per-face record slots (one array of N values per slot, per direction):
 // fluxes of the cell-averaged fields, then the quantities the edge EMF needs.
 // With the UCT-HLLD average, S_AP holds its weight om, S_AM its diffusion

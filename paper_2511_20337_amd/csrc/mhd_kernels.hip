@@ -91,22 +91,6 @@ __device__ __forceinline__ void tile_origin(const TileGrid& tg, unsigned t, int&
   k0 = tz * T::TZ;
 }
 
-// Workgroup order of the WENO-Z kernels (and of the mixed-mode EMF and update
-// kernels): the hardware deals workgroups
-// round-robin to the 8 XCDs, each with its own L2. Within every full group of
-// 512 workgroups, XCD x is given the 64 consecutive ones x*64 .. x*64+63, so
-// that neighbouring rows (the stencil's reach along y) are mostly read through
-// the same L2, while all XCDs still advance together through the domain and
-// share the Infinity Cache. A permutation of 0 .. nb-1; a last partial group
-// keeps its order. (Measured slower for the z-marching face kernel, whose
-// neighbouring columns share the Infinity Cache better round-robin.)
-__device__ __forceinline__ unsigned xcd_grouped(unsigned b, unsigned nb) {
-  const unsigned grp = b / 512u;
-  if ((grp + 1u) * 512u > nb) return b;
-  const unsigned w = b % 512u;
-  return grp * 512u + (w % 8u) * 64u + w / 8u;
-}
-
 // Cell of this thread in the row-tile traversal; false outside the domain.
 // XG: workgroups in the XCD-grouped order (xcd_grouped) instead of round-robin.
 template <bool XG = false>
