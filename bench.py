@@ -344,7 +344,7 @@ def main(argv=None):
     if args.only:
         return only_part(args.only, args.n, args.steps, args.warmup)
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
 
