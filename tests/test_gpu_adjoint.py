@@ -150,14 +150,23 @@ def test_adjoint_elementwise_special_states(dev, case, solver):
     assert dtbar == pytest.approx(float((ubar * jdt).sum()), rel=1e-11, abs=1e-14)
 
 
-@pytest.mark.parametrize("case", ["2d_32", "3d_12", "3d_16_minmod_hll", "3d_12_rk3", "2d_32_rk3"])
+@pytest.mark.parametrize("case", ["2d_32", "3d_12", "3d_16_minmod_hll", "3d_12_rk3", "2d_32_rk3",
+                                  "2d_400_ragged", "3d_60_ragged"])
 def test_adjoint_dot_product(dev, case):
+    # The ragged cases launch more than 512 workgroups (one full group of the
+    # XCD-grouped order and a partial one) on grids whose rows and planes are
+    # not multiples of the workgroup size.
     if case.startswith("2d_32"):
         s, U = smooth_ragged(2, 32, 28, 1, "vanleer", "hlld", seed=3)
     elif case.startswith("3d_12"):
         s, U = smooth_ragged(3, 12, 10, 11, "vanleer", "hlld", seed=4)
+    elif case == "2d_400_ragged":
+        s, U = smooth_ragged(2, 400, 397, 1, "vanleer", "hlld", seed=5)
+    elif case == "3d_60_ragged":
+        s, U = smooth_ragged(3, 60, 58, 50, "vanleer", "hlld", seed=5)
     else:
         s, U = smooth_ragged(3, 16, 16, 16, "minmod", "hll", seed=6)
+    print("adjoint dot product", case, U.shape, flush=True)
     if case.endswith("rk3"):
         s = dict(s, integrator="rk3")
     c = O.cfg_from(s)
