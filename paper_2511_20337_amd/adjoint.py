@@ -45,6 +45,9 @@ class MHDSteps(torch.autograd.Function):
         dts = fctx.dt_list
         n = len(dts)
         bar = gU.detach().contiguous().clone()
+        # dt-bar (its partial sums re-read the stage's records) only when the
+        # time steps require a gradient
+        want_dt = fctx.needs_input_grad[1]
         dtbar_dev = torch.zeros(n, dtype=torch.float64, device=bar.device)
         tmp = torch.empty_like(bar)
         for start in reversed(sorted(fctx.checkpoints)):
@@ -59,9 +62,9 @@ class MHDSteps(torch.autograd.Function):
                 states.append(U)
             for s in range(stop - 1, start - 1, -1):
                 solver.adjoint_step(states[s - start], dts[s], bar, out=tmp,
-                                    dtbar_out=dtbar_dev[s:s + 1])
+                                    dtbar_out=dtbar_dev[s:s + 1] if want_dt else None)
                 bar, tmp = tmp, bar
-        dtbar = dtbar_dev.cpu().reshape(fctx.dts_shape)
+        dtbar = dtbar_dev.cpu().reshape(fctx.dts_shape) if want_dt else None
         return bar, dtbar, None, None
 
 

@@ -774,9 +774,44 @@ __global__ __launch_bounds__(kBlock) void k_adj_cells(const double* __restrict__
   }
 }
 
-// ---------------------------------------------------------------------------
-// out = cd * Dir + s G + dt J^T (s G); per-block partial of <s G, L(U)>.
+// L(U) of cell (i,j,k) from the forward records, as the update kernel forms it.
 template <int DIM>
+__device__ __forceinline__ void stage_rhs(const double* __restrict__ FW,
+                                          const double* __restrict__ EW, const Geom& g, int i,
+                                          int j, int k, int64_t c, double* L) {
+  const int64_t n = g.n;
+  const int64_t xp = lin(g, wrap(i + 1, g.nx), j, k);
+  const int64_t yp = lin(g, i, wrap(j + 1, g.ny), k);
+  const int64_t zp = (DIM == 3) ? lin(g, i, j, wrap(k + 1, g.nz)) : c;
+  const double idx = 1.0 / g.dx, idy = 1.0 / g.dy, idz = 1.0 / g.dz;
+  const double* fx = FW;
+  const double* fy = FW + (int64_t)NSLOT * n;
+  const double* fz = FW + (int64_t)2 * NSLOT * n;
+  constexpr int ncell = (DIM == 3) ? 5 : 6;
+#pragma unroll
+  for (int q = 0; q < ncell; ++q) {
+    double acc = (fx[q * n + xp] - fx[q * n + c]) * idx + (fy[q * n + yp] - fy[q * n + c]) * idy;
+    if (DIM == 3) acc += (fz[q * n + zp] - fz[q * n + c]) * idz;
+    L[q == 5 ? 7 : q] = -acc;
+  }
+  if (DIM == 3) {
+    const double* ex = EW;
+    const double* ey = EW + n;
+    const double* ez = EW + 2 * n;
+    L[5] = -((ez[yp] - ez[c]) * idy - (ey[zp] - ey[c]) * idz);
+    L[6] = -((ex[zp] - ex[c]) * idz - (ez[xp] - ez[c]) * idx);
+    L[7] = -((ey[xp] - ey[c]) * idx - (ex[yp] - ex[c]) * idy);
+  } else {
+    const double* ez = EW + 2 * n;
+    L[5] = -((ez[yp] - ez[c]) * idy);
+    L[6] = (ez[xp] - ez[c]) * idx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// out = cd * Dir + s G + dt J^T (s G); DT: also the per-block partial of
+// <s G, L(U)> (L(U) from the forward records), which only dt-bar needs.
+template <int DIM, bool DT>
 __global__ __launch_bounds__(kBlock) void k_adj_final(const double* __restrict__ G, double s,
                                                       const double* __restrict__ Dir, double cd,
                                                       const double* __restrict__ FW,
@@ -802,43 +837,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(const double* __restrict__
     } else {
       jt[7] = bf.T[F_BZ * n + c];
     }
-    // L(U) from the forward records, as in the update kernel
-    const int64_t xp = lin(g, wrap(i + 1, g.nx), j, k);
-    const int64_t yp = lin(g, i, wrap(j + 1, g.ny), k);
-    const int64_t zp = (DIM == 3) ? lin(g, i, j, wrap(k + 1, g.nz)) : c;
-    const double idx = 1.0 / g.dx, idy = 1.0 / g.dy, idz = 1.0 / g.dz;
-    const double* fx = FW;
-    const double* fy = FW + (int64_t)NSLOT * n;
-    const double* fz = FW + (int64_t)2 * NSLOT * n;
-    double L[8];
-    constexpr int ncell = (DIM == 3) ? 5 : 6;
-#pragma unroll
-    for (int q = 0; q < ncell; ++q) {
-      double acc = (fx[q * n + xp] - fx[q * n + c]) * idx + (fy[q * n + yp] - fy[q * n + c]) * idy;
-      if (DIM == 3) acc += (fz[q * n + zp] - fz[q * n + c]) * idz;
-      L[q == 5 ? 7 : q] = -acc;
-    }
-    if (DIM == 3) {
-      const double* ex = EW;
-      const double* ey = EW + n;
-      const double* ez = EW + 2 * n;
-      L[5] = -((ez[yp] - ez[c]) * idy - (ey[zp] - ey[c]) * idz);
-      L[6] = -((ex[zp] - ex[c]) * idz - (ez[xp] - ez[c]) * idx);
-      L[7] = -((ey[xp] - ey[c]) * idx - (ex[yp] - ex[c]) * idy);
-    } else {
-      const double* ez = EW + 2 * n;
-      L[5] = -((ez[yp] - ez[c]) * idy);
-      L[6] = (ez[xp] - ez[c]) * idx;
-    }
+    double L[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (DT) stage_rhs<DIM>(FW, EW, g, i, j, k, c, L);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double sg = s * G[q * n + c];
       double v = sg + dt * jt[q];
       if (Dir) v += cd * Dir[q * n + c];
       out[q * n + c] = v;
-      dot += sg * L[q];
+      if constexpr (DT) dot += sg * L[q];
     }
   }
+  if constexpr (!DT) return;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
   __shared__ double red[kBlock / 64];
@@ -907,8 +917,12 @@ hipError_t stage_adjoint(const AdjointArgs& a, const Bufs& bf, const double* U, 
   hipLaunchKernelGGL((k_adj_faces<DIM, LIM, RS>), dim3(nb), dim3(kBlock), 0, a.stream, U, FW, G,
                      s, a.g, bf);
   hipLaunchKernelGGL((k_adj_cells<DIM, LIM>), dim3(nb), dim3(kBlock), 0, a.stream, U, a.g, bf);
-  hipLaunchKernelGGL((k_adj_final<DIM>), dim3(nb), dim3(kBlock), 0, a.stream, G, s, Dir, cd, FW,
-                     EW, a.g, a.dt, bf, out, part);
+  if (a.want_dtbar)
+    hipLaunchKernelGGL((k_adj_final<DIM, true>), dim3(nb), dim3(kBlock), 0, a.stream, G, s, Dir,
+                       cd, FW, EW, a.g, a.dt, bf, out, part);
+  else
+    hipLaunchKernelGGL((k_adj_final<DIM, false>), dim3(nb), dim3(kBlock), 0, a.stream, G, s, Dir,
+                       cd, FW, EW, a.g, a.dt, bf, out, part);
   return hipGetLastError();
 }
 
