@@ -144,10 +144,12 @@ def _run_gpu(ctx, U0, nsteps, dev):
 
 
 @pytest.mark.parametrize("case", ["orszag_tang_128", "turbulence_64", "blast_32",
-                                  "kh_64", "ragged2", "ragged3", "ragged3_runs"])
+                                  "kh_64", "ragged2", "ragged2_odd", "ragged3", "ragged3_runs"])
 def test_ten_step_parity_fp64(dev, case):
     """Ten CFL steps against the oracle. ragged3_runs (20 x 18 x 37) has
-    partial 16 x 16 columns in x and y and z-runs of 16, 16 and 5 planes."""
+    partial 16 x 16 columns in x and y and z-runs of 16, 16 and 5 planes. An
+    even nx takes the two-cell update kernel, an odd one (ragged2_odd 27 x 20,
+    ragged3 13 x 10 x 9) the one-cell kernel."""
     if case == "orszag_tang_128":
         s, U0 = W.orszag_tang_2d(128)
     elif case == "turbulence_64":
@@ -158,6 +160,8 @@ def test_ten_step_parity_fp64(dev, case):
         s, U0, _ = W.kelvin_helmholtz_2d(64)
     elif case == "ragged2":
         s, U0 = ragged(2, "minmod", "hlld")
+    elif case == "ragged2_odd":
+        s, U0 = W.generic_state(2, 27, 20, 1, "vanleer", "hlld", seed=4)
     elif case == "ragged3":
         s, U0 = ragged(3, "vanleer", "hll")
     else:
