@@ -59,7 +59,7 @@ FACE_TRAFFIC = {"fp64": 189.0 + 216.0, "mixed": 190.0 + 108.0}
 # HBM bytes per cell of one whole step, the same counters summed over its
 # launches (two of faces and EMF, the updates of both stages): what the
 # three-kernel stage moves beside the 320 algorithmic bytes.
-STEP_TRAFFIC = {"fp64": 1988.2, "mixed": 1322.6}
+STEP_TRAFFIC = {"fp64": 1984.7, "mixed": 1320.4}
 # WENO-Z face kernel on the 3D Orszag-Tang problem (FP64, HLLD): algorithmic
 # flops per cell of the oracle's face phase on that workload at 256^3 (count_flops.py;
 # its textbook WENO-Z with seven divisions per value, each one flop), and the
