@@ -65,7 +65,7 @@ STEP_TRAFFIC = {"fp64": 1984.7, "mixed": 1320.4}
 # its textbook WENO-Z with seven divisions per value, each one flop), and the
 # HBM bytes per cell counted at 352^3 (reads past L2 x2.0, writes x1.0).
 WENO_FACE_FLOPS = 4039.4
-WENO_FACE_TRAFFIC = 338.3 + 240.0
+WENO_FACE_TRAFFIC = 339.8 + 240.0
 
 
 def face_roofline(kt, ncell, precision="fp64"):
