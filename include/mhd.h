@@ -166,9 +166,10 @@ mhd_status mhd_step_device_dt(mhd_ctx* ctx, double* U, const double* dt_dev, voi
 
 /* One step of the configured integrator whose dt is the CFL time step of U
  * (as mhd_dt computes it, bit for bit), written to the device double *dt_dev
- * and used by the step; no host synchronisation. In 3D the CFL reduction runs
- * inside the first stage's face kernel (with WENO-Z, its primitive kernel)
- * instead of as a separate pass over U. */
+ * and used by the step; no host synchronisation. The CFL reduction runs
+ * inside the first stage's face kernel (in 3D with WENO-Z, its primitive
+ * kernel; with GLM, the GLM primitive kernel) instead of as a separate pass
+ * over U, except in 2D with WENO-Z, which keeps the separate pass. */
 mhd_status mhd_step_cfl(mhd_ctx* ctx, double* U, double* dt_dev, void* ws, size_t ws_bytes,
                         void* stream);
 

@@ -174,7 +174,7 @@ mhd::StageArgs stage_args(mhd_ctx* ctx, void* ws, hipStream_t s) {
   return a;
 }
 
-// One SSP-RK2 or SSP-RK3 step. dt_cfl (3D only): dt is the CFL step of U,
+// One SSP-RK2 or SSP-RK3 step. dt_cfl (not for 2D WENO-Z): dt is the CFL step of U,
 // reduced by the stage-1 face kernel and written to dt_cfl, which is also dtp.
 mhd_status run_step(mhd_ctx* ctx, double* U, double dt, const double* dtp, void* ws,
                     hipStream_t s, double* dt_cfl = nullptr) {
@@ -392,9 +392,9 @@ mhd_status mhd_step_cfl(mhd_ctx* ctx, double* U, double* dt_dev, void* ws, size_
   if (!U || !dt_dev) return MHD_ERR_INVALID;
   if (!ws_ok(ctx, ws, ws_bytes, false)) return MHD_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (ctx->cfg.dim == 3 || ctx->cfg.divb == MHD_DIVB_GLM)
+  if (ctx->cfg.dim == 3 || ctx->cfg.divb == MHD_DIVB_GLM || ctx->cfg.limiter != MHD_LIM_WENOZ)
     return run_step(ctx, U, 0.0, dt_dev, ws, s, dt_dev);
-  mhd_status st = cfl_to(ctx, U, ws, dt_dev, s);  // 2D: the separate CFL pass
+  mhd_status st = cfl_to(ctx, U, ws, dt_dev, s);  // 2D WENO-Z: the separate CFL pass
   if (st != MHD_OK) return st;
   return run_step(ctx, U, 0.0, dt_dev, ws, s);
 }

@@ -629,47 +629,6 @@ __device__ __forceinline__ void tile_face(const R (*sp)[Tile<DIM>::NPRIM], R bn,
   put_record<DIM, D, EM, R>(FW, g.n, c, o);
 }
 
-// Face kernel: primitives of the tile and its cross halo are recovered once
-// (in FP64) into LDS, held in the reconstruction precision R, then each
-// thread solves the lower x/y(/z) faces of its cell.
-template <int DIM, int LIM, int RS, class R, int EM>
-__global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* __restrict__ U,
-                                                        double* __restrict__ FW, Geom g,
-                                                        TileGrid tg, int* __restrict__ flag) {
-  static_assert(DIM == 2, "the 3D grid uses k_faces_march");
-  using T = Tile<DIM>;
-  __shared__ R sp[8][T::NPRIM];
-  int i0, j0, k0;
-  tile_origin<DIM>(tg, blockIdx.x, i0, j0, k0);
-  const int x = threadIdx.x % T::TX, y = (threadIdx.x / T::TX) % T::TY,
-            z = threadIdx.x / (T::TX * T::TY);
-  const int i = i0 + x, j = j0 + y, k = k0 + z;
-  const bool inside = i < g.nx && j < g.ny && k < g.nz;
-  // The normal fields of the cell's faces first (any in-bounds cell for a
-  // thread outside the grid): loaded after the x-face records, waiting for
-  // them would wait for those stores too.
-  const int64_t c = lin(g, min(i, g.nx - 1), min(j, g.ny - 1), min(k, g.nz - 1));
-  R bn[DIM];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) bn[d] = (R)U[(F_BX + d) * g.n + c];
-  bool bad = false;
-  for (int e = threadIdx.x; e < T::NPRIM; e += T::NCORE) {
-    int x, y, z;
-    pslot_pos<DIM>(e, x, y, z);
-    double V[8];
-    bad |= !prim_at<DIM>(U, g, wrap_any(i0 + x, g.nx), wrap_any(j0 + y, g.ny),
-                         wrap_any(k0 + z, g.nz), V);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sp[q][e] = (R)V[q];
-  }
-  if (bad) atomicOr(flag, 1);
-  __syncthreads();
-  if (!inside) return;
-  tile_face<DIM, 0, LIM, RS, R, EM>(sp, bn[0], FW, g, x, y, z, c);
-  tile_face<DIM, 1, LIM, RS, R, EM>(sp, bn[1], FW, g, x, y, z, c);
-  if (DIM == 3) tile_face<DIM, 2, LIM, RS, R, EM>(sp, bn[DIM - 1], FW, g, x, y, z, c);
-}
-
 // ---------------------------------------------------------------------------
 // CFL bound of one cell from its FP64 primitives: min over directions of
 // dx_d / (|v_d| + c_f,d), the expression of k_cfl.
@@ -703,6 +662,57 @@ __device__ __forceinline__ void workgroup_min_store(double v, double* __restrict
     for (int w = 1; w < kBlock / 64; ++w) r = (red[w] < r) ? red[w] : r;
     *out = r;
   }
+}
+
+// Face kernel: primitives of the tile and its cross halo are recovered once
+// (in FP64) into LDS, held in the reconstruction precision R, then each
+// thread solves the lower x/y(/z) faces of its cell. cflp != nullptr: also
+// the CFL bound of the state over the tile's own cells (the core, each cell
+// the own cell of exactly one tile) into cflp[blockIdx.x]; k_cfl_final
+// finishes it.
+template <int DIM, int LIM, int RS, class R, int EM>
+__global__ __launch_bounds__(Tile<DIM>::NCORE) void k_faces_tiled(const double* __restrict__ U,
+                                                        double* __restrict__ FW, Geom g,
+                                                        TileGrid tg, int* __restrict__ flag,
+                                                        double* __restrict__ cflp) {
+  static_assert(DIM == 2, "the 3D grid uses k_faces_march");
+  using T = Tile<DIM>;
+  static_assert(T::NCORE == kBlock, "workgroup_min_store reduces over kBlock threads");
+  __shared__ R sp[8][T::NPRIM];
+  int i0, j0, k0;
+  tile_origin<DIM>(tg, blockIdx.x, i0, j0, k0);
+  const int x = threadIdx.x % T::TX, y = (threadIdx.x / T::TX) % T::TY,
+            z = threadIdx.x / (T::TX * T::TY);
+  const int i = i0 + x, j = j0 + y, k = k0 + z;
+  const bool inside = i < g.nx && j < g.ny && k < g.nz;
+  // The normal fields of the cell's faces first (any in-bounds cell for a
+  // thread outside the grid): loaded after the x-face records, waiting for
+  // them would wait for those stores too.
+  const int64_t c = lin(g, min(i, g.nx - 1), min(j, g.ny - 1), min(k, g.nz - 1));
+  R bn[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) bn[d] = (R)U[(F_BX + d) * g.n + c];
+  bool bad = false;
+  double cmin = __builtin_inf();  // CFL bound of this thread's own cell
+  for (int e = threadIdx.x; e < T::NPRIM; e += T::NCORE) {
+    int x, y, z;
+    pslot_pos<DIM>(e, x, y, z);
+    double V[8];
+    bad |= !prim_at<DIM>(U, g, wrap_any(i0 + x, g.nx), wrap_any(j0 + y, g.ny),
+                         wrap_any(k0 + z, g.nz), V);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sp[q][e] = (R)V[q];
+    // the core comes first, thread t's first entry is its own cell
+    if (cflp && inside && e == (int)threadIdx.x) cmin = cfl_bound(g, V, cmin);
+  }
+  if (bad) atomicOr(flag, 1);
+  __syncthreads();
+  if (inside) {
+    tile_face<DIM, 0, LIM, RS, R, EM>(sp, bn[0], FW, g, x, y, z, c);
+    tile_face<DIM, 1, LIM, RS, R, EM>(sp, bn[1], FW, g, x, y, z, c);
+    if (DIM == 3) tile_face<DIM, 2, LIM, RS, R, EM>(sp, bn[DIM - 1], FW, g, x, y, z, c);
+  }
+  if (cflp) workgroup_min_store(cmin, cflp + blockIdx.x);
 }
 
 // Cell of this thread when each workgroup of kBlock threads takes kBlock
@@ -1464,7 +1474,12 @@ hipError_t stage_impl(const StageArgs& a) {
     const TileGrid tg = tile_grid<Tile<DIM>>(a.g);
     MHD_TIMED(a, K_FACES,
               hipLaunchKernelGGL((k_faces_tiled<DIM, LIM, RS, R, EM>), dim3(tg.ntiles),
-                                 dim3(Tile<DIM>::NCORE), 0, a.stream, a.U, a.FW, a.g, tg, a.flag));
+                                 dim3(Tile<DIM>::NCORE), 0, a.stream, a.U, a.FW, a.g, tg, a.flag,
+                                 a.cfl_partial));
+    if (a.cfl_partial)  // dt of the state U, before the update kernel reads it
+      MHD_TIMED(a, K_CFL_FINAL,
+                hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, a.cfl_partial,
+                                   (int)tg.ntiles, a.cfl, a.dt_out));
   }
   if constexpr (DIM == 3) {
     MarchGrid eg;
@@ -1574,6 +1589,7 @@ hipError_t stage_lim(const StageArgs& a) {
 
 size_t stage_cfl_blocks(const Geom& g, int limiter, bool glm) {
   if (glm || limiter == 2) return (size_t)((g.n + kBlock - 1) / kBlock);
+  if (g.nz == 1) return tile_grid<Tile<2>>(g).ntiles;  // 2D (3D grids have nz >= 4)
   return march_grid(g).nblocks;
 }
 
