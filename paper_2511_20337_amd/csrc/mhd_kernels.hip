@@ -449,6 +449,71 @@ __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict
   }
 }
 
+// 2D EMF and update in one kernel, over the row tiles of k_update: each
+// thread forms E_z at the lower corner of its cell (any thread past the grid
+// at the periodic image of that corner), threads 0..68 also the corners of
+// the row above and of the column to the right, all into LDS behind one
+// barrier; then each cell of the grid is updated as k_update<2> does it
+// (bitwise equal), and its own E_z is stored for the adjoint's records.
+template <int LIM, int STAGE, class R, int EM>
+__global__ __launch_bounds__(RowTile::NT) void k_emf_update_2d(const double* __restrict__ U,
+                                                               const double* U0, double* out,
+                                                               const double* __restrict__ FW,
+                                                               double* __restrict__ EW, Geom g,
+                                                               TileGrid tg, double dt,
+                                                               const double* __restrict__ dtp) {
+  constexpr int TX = RowTile::TX, TY = RowTile::TY, SX = TX + 1;
+  __shared__ R ezs[(TY + 1) * SX];
+  const unsigned t = (sizeof(R) == 4) ? xcd_grouped(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int i0 = (int)(t % (unsigned)tg.ntx) * TX;
+  const int j0 = (int)(t / (unsigned)tg.ntx) * TY;
+  const int x = (int)threadIdx.x % TX, y = (int)threadIdx.x / TX;
+  const int i = i0 + x, j = j0 + y;
+  const bool inside = i < g.nx && j < g.ny;
+  const int64_t n = g.n;
+  {
+    const int iw = wrap_any(i, g.nx), jw = wrap_any(j, g.ny);
+    const R ez = emf_comp<2, LIM, R, EM>(U, FW, g, iw, jw, 0, lin(g, iw, jw, 0));
+    ezs[y * SX + x] = ez;
+    if (inside) stored<R>(EW)[2 * n + lin(g, i, j, 0)] = ez;
+  }
+  if (threadIdx.x < TX + TY + 1) {
+    const int h = (int)threadIdx.x;
+    const int hx = (h < TX) ? h : TX, hy = (h < TX) ? TY : h - TX;  // h = TX + TY: the corner
+    const int iw = wrap_any(i0 + hx, g.nx), jw = wrap_any(j0 + hy, g.ny);
+    ezs[hy * SX + hx] = emf_comp<2, LIM, R, EM>(U, FW, g, iw, jw, 0, lin(g, iw, jw, 0));
+  }
+  __syncthreads();
+  if (!inside) return;
+  const int64_t c = lin(g, i, j, 0);
+  const double h = (STAGE == 0) ? 0.0 : (dtp ? *dtp : dt);
+  const int64_t xp = lin(g, wrap(i + 1, g.nx), j, 0);
+  const int64_t yp = lin(g, i, wrap(j + 1, g.ny), 0);
+  const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+  const R* fx = stored<R>(FW);
+  const R* fy = fx + (int64_t)NSLOT * n;
+  double L[8];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double acc = ((double)fx[q * n + xp] - (double)fx[q * n + c]) * idx +
+                       ((double)fy[q * n + yp] - (double)fy[q * n + c]) * idy;
+    L[q == 5 ? 7 : q] = -acc;
+  }
+  const double ezc = (double)ezs[y * SX + x];
+  L[5] = -(((double)ezs[(y + 1) * SX + x] - ezc) * idy);
+  L[6] = ((double)ezs[y * SX + x + 1] - ezc) * idx;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double v;
+    if (STAGE == 0) v = L[q];
+    else if (STAGE == 1) v = U[q * n + c] + h * L[q];
+    else if (STAGE == 4) v = (3.0 * U0[q * n + c] + (U[q * n + c] + h * L[q])) / 4.0;
+    else if (STAGE == 5) v = (U0[q * n + c] + 2.0 * (U[q * n + c] + h * L[q])) / 3.0;
+    else v = 0.5 * (U0[q * n + c] + (U[q * n + c] + h * L[q]));
+    out[q * n + c] = v;
+  }
+}
+
 // k_update for an even nx, two cells along x per thread (i even, i + 1) in
 // tiles of 128 x 4 cells: each array's values of the pair come as one
 // two-wide load (aligned: n, the offsets and i are even), the x neighbour of
@@ -1496,75 +1561,113 @@ hipError_t stage_impl(const StageArgs& a) {
       MHD_TIMED(a, K_EMF,
                 hipLaunchKernelGGL((k_emf_march<ELIM, R>), dim3(eg.nblocks), dim3(EmfCol::NT), 0,
                                    a.stream, a.U, a.FW, a.EW, a.g, eg));
-  } else {
+  } else if (a.stage == 3) {  // 2D records only; the 2D stages fuse the EMF into the update
     MHD_TIMED(a, K_EMF,
               hipLaunchKernelGGL((k_emf<DIM, ELIM, R, EM>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
                                  a.FW, a.EW, a.g, rg));
   }
-  if (a.g.nx % 2 == 0 && a.stage != 3) {
-    // even nx: the two-cell update (measured 0.979 -> 0.959 ms at 256^3 and
-    // 2.74 -> 2.56 ms at 352^3, FP64)
-    const TileGrid pg = tile_grid<PairTile>(a.g);
-    const unsigned pb = pg.ntiles;
+  if constexpr (DIM == 2) {
     switch (a.stage) {
+      case 3:
+        break;
       case 0:
         MHD_TIMED(a, K_UPDATE,
-                  hipLaunchKernelGGL((k_update2<DIM, 0, R>), dim3(pb), dim3(PairTile::NT), 0,
-                                     a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+                  hipLaunchKernelGGL((k_emf_update_2d<ELIM, 0, R, EM>), dim3(nb), dim3(RowTile::NT),
+                                     0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
+                                     a.dtp));
         break;
       case 1:
         MHD_TIMED(a, K_UPDATE,
-                  hipLaunchKernelGGL((k_update2<DIM, 1, R>), dim3(pb), dim3(PairTile::NT), 0,
-                                     a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+                  hipLaunchKernelGGL((k_emf_update_2d<ELIM, 1, R, EM>), dim3(nb), dim3(RowTile::NT),
+                                     0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
+                                     a.dtp));
         break;
       case 4:
         MHD_TIMED(a, K_UPDATE,
-                  hipLaunchKernelGGL((k_update2<DIM, 4, R>), dim3(pb), dim3(PairTile::NT), 0,
-                                     a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+                  hipLaunchKernelGGL((k_emf_update_2d<ELIM, 4, R, EM>), dim3(nb), dim3(RowTile::NT),
+                                     0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
+                                     a.dtp));
         break;
       case 5:
         MHD_TIMED(a, K_UPDATE,
-                  hipLaunchKernelGGL((k_update2<DIM, 5, R>), dim3(pb), dim3(PairTile::NT), 0,
-                                     a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+                  hipLaunchKernelGGL((k_emf_update_2d<ELIM, 5, R, EM>), dim3(nb), dim3(RowTile::NT),
+                                     0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
+                                     a.dtp));
         break;
       default:
         MHD_TIMED(a, K_UPDATE,
-                  hipLaunchKernelGGL((k_update2<DIM, 2, R>), dim3(pb), dim3(PairTile::NT), 0,
-                                     a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+                  hipLaunchKernelGGL((k_emf_update_2d<ELIM, 2, R, EM>), dim3(nb), dim3(RowTile::NT),
+                                     0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
+                                     a.dtp));
+        break;
+    }
+    return hipGetLastError();
+  } else {
+    if (a.g.nx % 2 == 0 && a.stage != 3) {
+      // even nx: the two-cell update (measured 0.979 -> 0.959 ms at 256^3 and
+      // 2.74 -> 2.56 ms at 352^3, FP64)
+      const TileGrid pg = tile_grid<PairTile>(a.g);
+      const unsigned pb = pg.ntiles;
+      switch (a.stage) {
+        case 0:
+          MHD_TIMED(a, K_UPDATE,
+                    hipLaunchKernelGGL((k_update2<DIM, 0, R>), dim3(pb), dim3(PairTile::NT), 0,
+                                       a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+          break;
+        case 1:
+          MHD_TIMED(a, K_UPDATE,
+                    hipLaunchKernelGGL((k_update2<DIM, 1, R>), dim3(pb), dim3(PairTile::NT), 0,
+                                       a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+          break;
+        case 4:
+          MHD_TIMED(a, K_UPDATE,
+                    hipLaunchKernelGGL((k_update2<DIM, 4, R>), dim3(pb), dim3(PairTile::NT), 0,
+                                       a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+          break;
+        case 5:
+          MHD_TIMED(a, K_UPDATE,
+                    hipLaunchKernelGGL((k_update2<DIM, 5, R>), dim3(pb), dim3(PairTile::NT), 0,
+                                       a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+          break;
+        default:
+          MHD_TIMED(a, K_UPDATE,
+                    hipLaunchKernelGGL((k_update2<DIM, 2, R>), dim3(pb), dim3(PairTile::NT), 0,
+                                       a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, pg, a.dt, a.dtp));
+          break;
+      }
+      return hipGetLastError();
+    }
+    switch (a.stage) {
+      case 3:  // face and edge records only (the adjoint's forward recompute)
+        break;
+      case 0:
+        MHD_TIMED(a, K_UPDATE,
+                  hipLaunchKernelGGL((k_update<DIM, 0, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                                     a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
+        break;
+      case 1:
+        MHD_TIMED(a, K_UPDATE,
+                  hipLaunchKernelGGL((k_update<DIM, 1, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                                     a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
+        break;
+      case 4:
+        MHD_TIMED(a, K_UPDATE,
+                  hipLaunchKernelGGL((k_update<DIM, 4, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                                     a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
+        break;
+      case 5:
+        MHD_TIMED(a, K_UPDATE,
+                  hipLaunchKernelGGL((k_update<DIM, 5, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                                     a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
+        break;
+      default:
+        MHD_TIMED(a, K_UPDATE,
+                  hipLaunchKernelGGL((k_update<DIM, 2, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
+                                     a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
         break;
     }
     return hipGetLastError();
   }
-  switch (a.stage) {
-    case 3:  // face and edge records only (the adjoint's forward recompute)
-      break;
-    case 0:
-      MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 0, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
-                                   a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
-      break;
-    case 1:
-      MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 1, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
-                                   a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
-      break;
-    case 4:
-      MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 4, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
-                                   a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
-      break;
-    case 5:
-      MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 5, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
-                                   a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
-      break;
-    default:
-      MHD_TIMED(a, K_UPDATE,
-                hipLaunchKernelGGL((k_update<DIM, 2, R>), dim3(nb), dim3(RowTile::NT), 0, a.stream, a.U,
-                                   a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt, a.dtp));
-      break;
-  }
-  return hipGetLastError();
 }
 
 template <int DIM, int EM>
