@@ -147,9 +147,10 @@ def _run_gpu(ctx, U0, nsteps, dev):
                                   "kh_64", "ragged2", "ragged2_odd", "ragged3", "ragged3_runs"])
 def test_ten_step_parity_fp64(dev, case):
     """Ten CFL steps against the oracle. ragged3_runs (20 x 18 x 37) has
-    partial 16 x 16 columns in x and y and z-runs of 16, 16 and 5 planes. An
-    even nx takes the two-cell update kernel, an odd one (ragged2_odd 27 x 20,
-    ragged3 13 x 10 x 9) the one-cell kernel."""
+    partial 16 x 16 columns in x and y and z-runs of 16, 16 and 5 planes. In
+    3D an even nx takes the two-cell update kernel, an odd one (ragged3
+    13 x 10 x 9) the one-cell kernel; 2D grids (ragged2_odd 27 x 20 with a
+    partial tile among them) the kernel that forms the EMF with the update."""
     if case == "orszag_tang_128":
         s, U0 = W.orszag_tang_2d(128)
     elif case == "turbulence_64":
