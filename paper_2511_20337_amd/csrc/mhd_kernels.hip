@@ -455,15 +455,34 @@ __global__ __launch_bounds__(RowTile::NT) void k_update(const double* __restrict
 // the row above and of the column to the right, all into LDS behind one
 // barrier; then each cell of the grid is updated as k_update<2> does it
 // (bitwise equal), and its own E_z is stored for the adjoint's records.
+// cflp != nullptr (first stage of a step whose face kernel left npart CFL
+// partials): every workgroup reduces the partials itself to the minimum
+// k_cfl_final forms (a minimum is exact in any order), dt = cfl * min, and
+// workgroup 0 writes it to *dt_out; for small grids this replaces the
+// k_cfl_final launch.
 template <int LIM, int STAGE, class R, int EM>
 __global__ __launch_bounds__(RowTile::NT) void k_emf_update_2d(const double* __restrict__ U,
                                                                const double* U0, double* out,
                                                                const double* __restrict__ FW,
                                                                double* __restrict__ EW, Geom g,
                                                                TileGrid tg, double dt,
-                                                               const double* __restrict__ dtp) {
+                                                               const double* __restrict__ dtp,
+                                                               const double* __restrict__ cflp,
+                                                               int npart, double cfl,
+                                                               double* __restrict__ dt_out) {
   constexpr int TX = RowTile::TX, TY = RowTile::TY, SX = TX + 1;
   __shared__ R ezs[(TY + 1) * SX];
+  __shared__ double red[RowTile::NT / 64];
+  if (cflp) {
+    double m = __builtin_inf();
+    for (int b = (int)threadIdx.x; b < npart; b += RowTile::NT) m = (cflp[b] < m) ? cflp[b] : m;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(m, off, 64);
+      m = (o < m) ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  }
   const unsigned t = (sizeof(R) == 4) ? xcd_grouped(blockIdx.x, gridDim.x) : blockIdx.x;
   const int i0 = (int)(t % (unsigned)tg.ntx) * TX;
   const int j0 = (int)(t / (unsigned)tg.ntx) * TY;
@@ -484,9 +503,20 @@ __global__ __launch_bounds__(RowTile::NT) void k_emf_update_2d(const double* __r
     ezs[hy * SX + hx] = emf_comp<2, LIM, R, EM>(U, FW, g, iw, jw, 0, lin(g, iw, jw, 0));
   }
   __syncthreads();
+  double h;
+  if (STAGE == 0) {
+    h = 0.0;
+  } else if (cflp) {
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < RowTile::NT / 64; ++w) m = (red[w] < m) ? red[w] : m;
+    h = cfl * m;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dt_out = h;
+  } else {
+    h = dtp ? *dtp : dt;
+  }
   if (!inside) return;
   const int64_t c = lin(g, i, j, 0);
-  const double h = (STAGE == 0) ? 0.0 : (dtp ? *dtp : dt);
   const int64_t xp = lin(g, wrap(i + 1, g.nx), j, 0);
   const int64_t yp = lin(g, i, wrap(j + 1, g.ny), 0);
   const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
@@ -907,6 +937,9 @@ static_assert(March::NHALO <= March::NCORE, "at most one halo cell per thread");
 // Planes per run: the prologue costs two extra planes per run, shorter runs
 // give more workgroups (4096 at 256^3 with 16; 16 measured faster than 32).
 constexpr int kMarchRun = 16;
+// Most CFL partials (2D tiles) that every workgroup of the first stage's
+// update reduces itself instead of a k_cfl_final launch (1024: KH 512^2).
+constexpr unsigned kUpdateCflMax = 1024;
 
 // 73.5 KB in FP64: two workgroups (eight waves) per CU.
 template <class R>
@@ -1541,7 +1574,9 @@ hipError_t stage_impl(const StageArgs& a) {
               hipLaunchKernelGGL((k_faces_tiled<DIM, LIM, RS, R, EM>), dim3(tg.ntiles),
                                  dim3(Tile<DIM>::NCORE), 0, a.stream, a.U, a.FW, a.g, tg, a.flag,
                                  a.cfl_partial));
-    if (a.cfl_partial)  // dt of the state U, before the update kernel reads it
+    // dt of the state U before the update reads it: for a few partials the
+    // update's workgroups reduce them themselves, else k_cfl_final
+    if (a.cfl_partial && tg.ntiles > kUpdateCflMax)
       MHD_TIMED(a, K_CFL_FINAL,
                 hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, a.stream, a.cfl_partial,
                                    (int)tg.ntiles, a.cfl, a.dt_out));
@@ -1567,6 +1602,10 @@ hipError_t stage_impl(const StageArgs& a) {
                                  a.FW, a.EW, a.g, rg));
   }
   if constexpr (DIM == 2) {
+    // the stage-1 CFL partials of the tiled face kernel, when few
+    const unsigned ntile = tile_grid<Tile<DIM>>(a.g).ntiles;
+    const double* ucfl = (a.cfl_partial && ntile <= kUpdateCflMax) ? a.cfl_partial : nullptr;
+    const int unp = (int)ntile;
     switch (a.stage) {
       case 3:
         break;
@@ -1574,31 +1613,31 @@ hipError_t stage_impl(const StageArgs& a) {
         MHD_TIMED(a, K_UPDATE,
                   hipLaunchKernelGGL((k_emf_update_2d<ELIM, 0, R, EM>), dim3(nb), dim3(RowTile::NT),
                                      0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
-                                     a.dtp));
+                                     a.dtp, ucfl, unp, a.cfl, a.dt_out));
         break;
       case 1:
         MHD_TIMED(a, K_UPDATE,
                   hipLaunchKernelGGL((k_emf_update_2d<ELIM, 1, R, EM>), dim3(nb), dim3(RowTile::NT),
                                      0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
-                                     a.dtp));
+                                     a.dtp, ucfl, unp, a.cfl, a.dt_out));
         break;
       case 4:
         MHD_TIMED(a, K_UPDATE,
                   hipLaunchKernelGGL((k_emf_update_2d<ELIM, 4, R, EM>), dim3(nb), dim3(RowTile::NT),
                                      0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
-                                     a.dtp));
+                                     a.dtp, ucfl, unp, a.cfl, a.dt_out));
         break;
       case 5:
         MHD_TIMED(a, K_UPDATE,
                   hipLaunchKernelGGL((k_emf_update_2d<ELIM, 5, R, EM>), dim3(nb), dim3(RowTile::NT),
                                      0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
-                                     a.dtp));
+                                     a.dtp, ucfl, unp, a.cfl, a.dt_out));
         break;
       default:
         MHD_TIMED(a, K_UPDATE,
                   hipLaunchKernelGGL((k_emf_update_2d<ELIM, 2, R, EM>), dim3(nb), dim3(RowTile::NT),
                                      0, a.stream, a.U, a.U0, a.out, a.FW, a.EW, a.g, rg, a.dt,
-                                     a.dtp));
+                                     a.dtp, ucfl, unp, a.cfl, a.dt_out));
         break;
     }
     return hipGetLastError();

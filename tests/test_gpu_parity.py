@@ -333,15 +333,17 @@ def test_device_dt_path_matches_host_dt(dev):
 
 
 @pytest.mark.parametrize("case", ["ragged3_runs", "short_runs", "mixed", "ragged2", "ot2d_128",
-                                  "rk3", "wenoz", "wenoz2"])
+                                  "ragged2_1122", "rk3", "wenoz", "wenoz2"])
 def test_step_cfl_matches_separate_cfl_pass(dev, case):
     """mhd_step_cfl (the CFL reduction inside the first face kernel) gives
     the dt of mhd_dt_device and the state of mhd_step_device_dt, bit for bit,
     and that dt is the oracle's. ragged3_runs: 20 x 18 x 37 (z-runs of 16, 16,
     5 planes; partial columns); short_runs: 12 x 10 x 7 (one run shorter than
     16); mixed: the first state in mixed precision; ragged2: 2D 28 x 20 (the
-    reduction in the tiled face kernel; partial 16 x 16 tiles); ot2d_128: 64
-    whole tiles; wenoz: the reduction in the WENO-Z primitive kernel (53
+    reduction in the tiled face kernel, finished by every workgroup of the
+    update; partial 16 x 16 tiles); ot2d_128: 64 whole tiles; ragged2_1122:
+    530 x 520, 1122 tiles, more than the update finishes itself, so
+    k_cfl_final does; wenoz: the reduction in the WENO-Z primitive kernel (53
     workgroups of 256 cells, the last one holding 8); wenoz2: 2D WENO-Z with
     the separate pass."""
     if case == "ragged3_runs":
@@ -360,6 +362,8 @@ def test_step_cfl_matches_separate_cfl_pass(dev, case):
         s, U0 = ragged(2, "wenoz", "hlld")
     elif case == "ot2d_128":
         s, U0 = W.orszag_tang_2d(128)
+    elif case == "ragged2_1122":
+        s, U0 = W.generic_state(2, 530, 520, 1, "vanleer", "hlld", seed=6)
     else:
         s, U0 = ragged(2, "minmod", "hlld")
     print("step_cfl", case, flush=True)
